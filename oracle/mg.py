@@ -101,10 +101,12 @@ def eps_numerator(grid, x, opts):
 
 
 def fd_jv(problem, grid, x, Ax, v, m, eps):
-    """(A(x + eps v) - A(x)) / eps on the DoFs (Sec. 1)."""
+    """(A(x + eps v) - A(x)) / eps on the DoFs (Sec. 1); v acts on the DoFs
+    only (Dirichlet entries of v are ignored: they are not unknowns)."""
     if eps == 0.0:
         return np.zeros_like(v)
-    return (apply_A(problem, grid, x + eps * v, m) - Ax) / eps
+    nc = 1 if v.ndim == grid.dim else v.shape[0]
+    return (apply_A(problem, grid, x + eps * _mask(grid, nc, v), m) - Ax) / eps
 
 
 def level_jv(problem, lev, v, stats=None, level=None):
