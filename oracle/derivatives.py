@@ -75,7 +75,7 @@ def _neohooke_jvp(grid, ue, ve, prm):
     out = np.zeros_like(ue)
     for q in range(len(w)):
         B = dphi[q] / grid.h
-        Fd = _deformation(grid, ue, q)
+        Fd = _deformation(grid.h, ue, q)
         dF = np.einsum('ia...,aj->...ij', ve, B)
         J = np.linalg.det(Fd)
         Finv = np.linalg.inv(Fd)

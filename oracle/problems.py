@@ -70,13 +70,17 @@ def _mask(grid, ncomp, v):
 # ---------------------------------------------------------------------------
 def element_vectors(problem, grid, u, m=None):
     """r_e for every element: shape (2^d,)+elem_shape, or (3, 8)+elem_shape."""
-    dim, h = grid.dim, grid.h
+    me = grid.gather(m) if problem.kind == 'invcoef' else None
+    return element_vectors_from_corners(problem, grid.dim, grid.h, grid.gather(u), me)
+
+
+def element_vectors_from_corners(problem, dim, h, ue, me=None):
+    """r_e from corner values ue (2^d, ...) or (3, 8, ...); me: corner m values."""
     kind, prm = problem.kind, problem.params
     K = element_stiffness(dim, h)
     vol = h ** dim
     if kind == 'neohooke':
-        return _neohooke_vectors(grid, grid.gather(u), prm)
-    ue = grid.gather(u)
+        return _neohooke_vectors(h, ue, prm)
     Ku = np.einsum('ab,b...->a...', K, ue)
     if kind == 'bratu':
         phi, _, w, _ = reference_rule(dim)
@@ -97,33 +101,32 @@ def element_vectors(problem, grid, u, m=None):
             out += w[q] * vol * kq * np.einsum('ak,k...->a...', dphi[q] / h, g)
         return out
     if kind == 'invcoef':
-        me = grid.gather(m)
         kbar = np.mean(np.exp(me), axis=0)
         ubar = np.mean(ue, axis=0)
         return kbar * (1.0 + ubar ** 2) * Ku
     raise ValueError(kind)
 
 
-def _deformation(grid, ue, q):
+def _deformation(h, ue, q):
     """Fd = I + grad u at Gauss point q in every element, shape elem+(3,3)."""
     _, dphi, _, _ = reference_rule(3)
-    G = np.einsum('ia...,aj->...ij', ue, dphi[q] / grid.h)
+    G = np.einsum('ia...,aj->...ij', ue, dphi[q] / h)
     return np.eye(3) + G
 
 
-def _neohooke_vectors(grid, ue, prm):
+def _neohooke_vectors(h, ue, prm):
     mu, lam = lame(prm['E'], prm['nu'])
     _, dphi, w, _ = reference_rule(3)
-    vol = grid.h ** 3
+    vol = h ** 3
     out = np.zeros_like(ue)
     for q in range(len(w)):
-        Fd = _deformation(grid, ue, q)
+        Fd = _deformation(h, ue, q)
         J = np.linalg.det(Fd)
         with np.errstate(invalid='ignore', divide='ignore'):
             lnJ = np.where(J > 0, np.log(np.where(J > 0, J, 1.0)), np.nan)
         FinvT = np.swapaxes(np.linalg.inv(Fd), -1, -2)
         P = mu * (Fd - FinvT) + (lam * lnJ)[..., None, None] * FinvT
-        out += w[q] * vol * np.einsum('...ij,aj->ia...', P, dphi[q] / grid.h)
+        out += w[q] * vol * np.einsum('...ij,aj->ia...', P, dphi[q] / h)
     return out
 
 
@@ -143,6 +146,47 @@ def residual(problem, grid, u, b, m=None):
     return _mask(grid, problem.ncomp, A - b) if b is not None else A
 
 
+def residual_at(problem, grid, u, b, nodes, m=None):
+    """F at selected nodes only (flat node indices), by summing the element
+    vectors of the elements around each node; for checks at sizes where a
+    full assembly is too slow.  Returns (ncomp, len(nodes)) or (len(nodes),)."""
+    nodes = np.asarray(nodes)
+    d = grid.dim
+    coords = np.unravel_index(nodes, grid.node_shape)            # (z, y, x) order
+    xyz = [coords[d - 1 - k] for k in range(d)]                   # x, y[, z]
+    nc = problem.ncomp
+    out = np.zeros((nc, nodes.size))
+    uf = u.reshape((nc, -1)) if nc > 1 else u.reshape((1, -1))
+    mf = m.reshape(-1) if m is not None else None
+    for e in range(2 ** d):
+        bits = [(e >> k) & 1 for k in range(d)]
+        org = [xyz[k] - bits[k] for k in range(d)]
+        ok = np.ones(nodes.size, dtype=bool)
+        for k in range(d):
+            ok &= (org[k] >= 0) & (org[k] < grid.n[k])
+        if not ok.any():
+            continue
+        corner_idx = []
+        for a in range(2 ** d):
+            ab = [(a >> k) & 1 for k in range(d)]
+            c = [np.where(ok, org[k], 0) + ab[k] for k in range(d)]
+            corner_idx.append(np.ravel_multi_index(tuple(reversed(c)), grid.node_shape))
+        corner_idx = np.array(corner_idx)                          # (2^d, N)
+        ue = uf[:, corner_idx] if nc > 1 else uf[0][corner_idx]
+        me = mf[corner_idx] if mf is not None else None
+        re = element_vectors_from_corners(problem, d, grid.h, ue, me)
+        if nc > 1:
+            out += np.where(ok, re[:, e], 0.0)
+        else:
+            out[0] += np.where(ok, re[e], 0.0)
+    dm = grid.dirichlet_mask().reshape(-1)[nodes]
+    if b is not None:
+        bf = b.reshape((nc, -1)) if nc > 1 else b.reshape((1, -1))
+        out -= bf[:, nodes]
+    out[:, dm] = 0.0
+    return out if nc > 1 else out[0]
+
+
 def energy(problem, grid, u, b=None):
     """Psi_h(u) - b.u for the variational problems."""
     dim, h = grid.dim, grid.h
@@ -156,7 +200,7 @@ def energy(problem, grid, u, b=None):
         ue = grid.gather(u)
         tot = 0.0
         for q in range(len(w)):
-            Fd = _deformation(grid, ue, q)
+            Fd = _deformation(grid.h, ue, q)
             J = np.linalg.det(Fd)
             if np.any(J <= 0):
                 return np.inf
