@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark: DoF/s to a 1e-8 relative nonlinear residual on one MI355X.
+
+Workload (default plap3d-256): the regularised p-Laplacian (p = 3,
+delta = 1e-2) on the unit cube, 256^3 Q1 elements (16,581,375 DoFs), load =
+16 seeded Gaussians, 6 multigrid levels, Chebyshev degree 4, FGMRES(30).
+One step = one full inexact-Newton solve from u = 0 to ||F|| <= 1e-8 ||F_0||
+with the FP32 V-cycle (FP64 outer Newton, outer FD Jv, Arnoldi and norms).
+The same solve with FP64 levels is timed for comparison.
+
+Printed JSON line: value = DoF / (seconds per solve) of the FP32-multigrid
+solve; roofline = the fine-level kernel class with the largest share of the
+timed region, measured with HIP events around each of its launches;
+fine_residual = FP64 F(u) GB/s over rotating buffers; cpu_baseline = the
+NumPy oracle on the host (see --help).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print('[bench]', *a, file=sys.stderr, flush=True)
+
+
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic bytes per fine node of each timed kernel class
+BYTES_PER_NODE = {
+    'cheb_step_f32': 8 * 4,   # reads x, A(x), d, r, s; writes r, s, d'
+    'cheb_step_f64': 8 * 8,
+    'outer_jv': 8 + 8 + 4 + 8,   # reads u, A(u) (FP64), z (FP32); writes Jv (FP64)
+    'outer_jv_f64': 4 * 8,
+    'resid_fine': 4 * 8,      # reads u, b; writes F and A(u)
+}
+
+
+def build_problem(w):
+    from paper_2103_13890_amd import api
+    return api.make_problem(w['kind'], w['n'], w['h'], w['faces'], w['params'], w['nlevels'])
+
+
+def make_load(ctx, w):
+    from paper_2103_13890_amd import api
+    from paper_2103_13890_amd import workloads as W
+    c, wd, a = W.gaussian_params(w.get('load_seed', 1), 16, len(w['n']))
+    return api.jfnk_assemble_load(ctx, 0, W.gaussian_param_array(c, wd, a))
+
+
+def timed_solves(ctx, b, steps, warmup, timers=True):
+    import torch
+    from paper_2103_13890_amd import api
+    from paper_2103_13890_amd import _lib
+    u = ctx.empty(ctx.nlevels - 1)
+    for i in range(warmup):
+        u.zero_()
+        rep = api.jfnk_solve(ctx, u, None, b)
+        log(f'warmup {i}: {rep["status"]} newton {rep["newton_iters"]} krylov {rep["linear_iters"]} '
+            f'{rep["time_ms"]:.1f} ms')
+    tids = [_lib.TIMER_CHEB_FINE, _lib.TIMER_JV_OUTER, _lib.TIMER_RESID_FINE, _lib.TIMER_ARNOLDI]
+    if timers:
+        for t in tids:
+            api.jfnk_timer_enable(ctx, t, True)
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        u.zero_()
+        reps.append(api.jfnk_solve(ctx, u, None, b))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = {}
+    if timers:
+        for t in tids:
+            tim[t] = api.jfnk_timer_read(ctx, t)
+            api.jfnk_timer_enable(ctx, t, False)
+    for i, r in enumerate(reps):
+        log(f'step {i}: {r["status"]} newton {r["newton_iters"]} krylov {r["linear_iters"]} '
+            f'GE {r["ge_effective"]:.1f} {r["time_ms"]:.1f} ms')
+    return u, reps, (t1 - t0) / steps, tim
+
+
+def residual_gbps(ctx, w, nsets=4, launches=100):
+    """FP64 F(u) on the finest level, rotating over nsets buffer sets."""
+    import torch
+    from paper_2103_13890_amd import api
+    from paper_2103_13890_amd import _lib
+    L = ctx.nlevels - 1
+    sets = []
+    for k in range(nsets):
+        u = torch.rand(ctx.node_shape(L), dtype=torch.float64, device=ctx.device) * 0.1
+        b = torch.rand_like(u) * 1e-6
+        sets.append((u, b, torch.empty_like(u)))
+    for k in range(nsets):
+        api.jfnk_residual(ctx, L, sets[k][0], None, sets[k][1], sets[k][2])
+    api.jfnk_timer_enable(ctx, _lib.TIMER_RESID_FINE, True)
+    for i in range(launches):
+        u, b, F = sets[i % nsets]
+        api.jfnk_residual(ctx, L, u, None, b, F)
+    cnt, ms = api.jfnk_timer_read(ctx, _lib.TIMER_RESID_FINE)
+    api.jfnk_timer_enable(ctx, _lib.TIMER_RESID_FINE, False)
+    _, nn, _ = ctx.level_info(L)
+    avg = ms / cnt
+    gbs = 24.0 * nn / (avg * 1e-3) / 1e9
+    del sets
+    return {'gbps': gbs, 'frac': gbs / HBM_PEAK_GBS, 'avg_us': avg * 1e3, 'launches': cnt,
+            'bytes_per_launch': 24 * nn, 'buffers': f'{nsets} rotating sets of u, b, F (FP64)'}
+
+
+def cpu_baseline(w, ge_effective, ndof):
+    """Oracle sample: fine-level F(u) evaluations at full size on the host."""
+    from oracle.fe import Grid
+    from oracle.problems import Problem, residual
+    from paper_2103_13890_amd import workloads as W
+    g = Grid(w['n'], w['h'], w['faces'])
+    pb = Problem('plap', {'p': w['params'][0], 'delta': w['params'][1]})
+    u = 0.01 * W.rough_state(w['n'], w['faces'], 7)
+    b = np.zeros_like(u)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        residual(pb, g, u, b)
+        k += 1
+        if time.perf_counter() - t0 > 10.0 or k >= 3:
+            break
+    per = (time.perf_counter() - t0) / k
+    est = per * ge_effective
+    return {'value': ndof / est, 'unit': 'DoF/s', 'cores': 1, 'kind': 'oracle',
+            'sample': (f'{k} fine-level F(u) evaluations of the NumPy oracle at 256^3 ({per:.2f} s each, '
+                       f'single-threaded), scaled by the {ge_effective:.0f} effective gradient evaluations '
+                       f'(GE, Sec. 3) of the FP64-multigrid GPU solve; Krylov, transfer and coarse-solve '
+                       f'work not included, so this over-estimates the oracle rate')}
+
+
+def sampled_check(ctx, w, u, b, nsamp=4096):
+    """Oracle residual at sampled nodes vs. the GPU residual there."""
+    from oracle.fe import Grid
+    from oracle.problems import Problem, residual_at
+    from paper_2103_13890_amd import api
+    g = Grid(w['n'], w['h'], w['faces'])
+    pb = Problem('plap', {'p': w['params'][0], 'delta': w['params'][1]})
+    L = ctx.nlevels - 1
+    F = api.jfnk_residual(ctx, L, u, None, b).cpu().numpy().reshape(-1)
+    un, bn = u.cpu().numpy(), b.cpu().numpy()
+    rng = np.random.default_rng(5)
+    nodes = rng.choice(g.n_nodes, nsamp, replace=False)
+    Fo = residual_at(pb, g, un, bn, nodes)
+    return float(np.max(np.abs(F[nodes] - Fo)) / max(np.max(np.abs(Fo)), 1e-300))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=3)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--workload', default='plap3d-256')
+    ap.add_argument('--no-fp64', action='store_true', help='skip the FP64-multigrid comparison solve')
+    ap.add_argument('--no-cpu', action='store_true', help='skip the oracle CPU baseline')
+    ap.add_argument('--kernel-path', type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
+        print('bench.py runs on exactly one GPU: this build has no multi-GPU path '
+              '(sharding is described in DESIGN.md)', file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2103_13890_amd import api
+    from paper_2103_13890_amd import workloads as W
+
+    w = W.WORKLOADS[args.workload]
+    prob = build_problem(w)
+    opts32 = api.default_options(**dict(w['options'], vcycle_prec=1, coarse_rtol=1e-3,
+                                        kernel_path=args.kernel_path))
+    log(f'workload {args.workload}: creating FP32-multigrid context')
+    ctx = api.Context(prob, opts32)
+    L = ctx.nlevels - 1
+    _, nn, ndof = ctx.level_info(L)
+    b = make_load(ctx, w)
+    u32, reps32, sec32, tim = timed_solves(ctx, b, args.steps, args.warmup)
+    value = ndof / sec32
+    ok32 = all(r['status'] == 'ok' for r in reps32)
+    # roofline of the dominant fine-level kernel class in the timed region
+    from paper_2103_13890_amd import _lib
+    cls = {_lib.TIMER_CHEB_FINE: 'cheb_step_f32', _lib.TIMER_JV_OUTER: 'outer_jv',
+           _lib.TIMER_RESID_FINE: 'resid_fine'}
+    shares = {cls[t]: tim[t] for t in cls}
+    dom = max(shares, key=lambda k: shares[k][1])
+    cnt, ms = shares[dom]
+    avg_ms = ms / max(cnt, 1)
+    achieved = BYTES_PER_NODE[dom] * nn / (avg_ms * 1e-3) / 1e9
+    arn_cnt, arn_ms = tim[_lib.TIMER_ARNOLDI]
+    roofline = {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+                'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None, 'kernel': dom,
+                'avg_launch_us': round(avg_ms * 1e3, 2), 'launches': cnt,
+                'bytes_per_launch': BYTES_PER_NODE[dom] * nn,
+                'share_of_step': round(ms / (sec32 * 1e3 * args.steps), 4)}
+    kernel_shares = {k: {'launches': v[0], 'ms_total': round(v[1], 3),
+                         'share': round(v[1] / (sec32 * 1e3 * args.steps), 4)} for k, v in shares.items()}
+    kernel_shares['arnoldi_cgs2'] = {'launches': arn_cnt, 'ms_total': round(arn_ms, 3),
+                                     'share': round(arn_ms / (sec32 * 1e3 * args.steps), 4)}
+    ge32 = reps32[-1]['ge_effective']
+    log(f'FP32-MG: {sec32 * 1e3:.1f} ms/solve, {value:.3e} DoF/s, dominant {dom} {achieved:.0f} GB/s')
+
+    extra = {}
+    u64 = None
+    if not args.no_fp64:
+        del ctx
+        torch.cuda.empty_cache()
+        opts64 = api.default_options(**dict(w['options'], vcycle_prec=0, coarse_rtol=1e-6,
+                                            kernel_path=args.kernel_path))
+        log('creating FP64-multigrid context')
+        ctx64 = api.Context(prob, opts64)
+        b64 = make_load(ctx64, w)
+        u64, reps64, sec64, _ = timed_solves(ctx64, b64, args.steps, args.warmup, timers=False)
+        ok64 = all(r['status'] == 'ok' for r in reps64)
+        extra['fp64_mg'] = {'value': ndof / sec64, 'ms_per_step': sec64 * 1e3, 'ok': ok64,
+                            'newton': reps64[-1]['newton_iters'], 'krylov': reps64[-1]['linear_iters'],
+                            'ge_effective': reps64[-1]['ge_effective'],
+                            'final_rel_residual': reps64[-1]['fnorm'] / reps64[-1]['fnorm0']}
+        extra['fp32_over_fp64_speedup'] = sec64 / sec32
+        extra['rel_diff_fp32_vs_fp64_solution'] = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        log(f'FP64-MG: {sec64 * 1e3:.1f} ms/solve; speedup {sec64 / sec32:.2f}')
+        # tight FP64 reference solve (the oracle-matched solver at 1e-12) for the error statement
+        del ctx64
+        torch.cuda.empty_cache()
+        opts_t = api.default_options(**dict(w['options'], vcycle_prec=0, coarse_rtol=1e-6, newton_rtol=1e-12,
+                                            kernel_path=args.kernel_path))
+        ctxt = api.Context(prob, opts_t)
+        ut = ctxt.empty(L)
+        rt = api.jfnk_solve(ctxt, ut, None, b64)
+        extra['rel_err_vs_tight_fp64_solution'] = {
+            'fp32_mg': float(torch.linalg.norm(u32 - ut) / torch.linalg.norm(ut)),
+            'fp64_mg': float(torch.linalg.norm(u64 - ut) / torch.linalg.norm(ut)),
+            'tight_status': rt['status']}
+        fres = residual_gbps(ctxt, w)
+        extra['fine_residual_f64'] = fres
+        log(f'fine F(u) FP64: {fres["gbps"]:.0f} GB/s ({fres["avg_us"]:.1f} us)')
+        try:
+            extra['oracle_sampled_residual_rel_diff'] = sampled_check(ctxt, w, u32, b64)
+        except Exception as e:      # the check is informative only
+            extra['oracle_sampled_residual_rel_diff'] = f'skipped: {e}'
+        del ctxt
+    cpu = None
+    if not args.no_cpu:
+        ge_ref = extra.get('fp64_mg', {}).get('ge_effective', ge32)
+        log('timing the oracle sample on the host')
+        cpu = cpu_baseline(w, ge_ref, ndof)
+
+    out = {
+        'metric': 'DoF/s to 1e-8 nonlinear residual, FP32-MG vs FP64-MG; fine F(u) HBM GB/s',
+        'value': value, 'unit': 'DoF/s', 'n_gpus': 1, 'steps': args.steps, 'warmup': args.warmup,
+        'ms_per_step': sec32 * 1e3, 'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None,
+        'dtype': 'f64 outer / f32 multigrid', 'data': 'synthetic',
+        'config': {'workload': args.workload, 'elements': list(w['n']), 'dofs': ndof, 'levels': w['nlevels'],
+                   'cheb_degree': w['options']['nu_pre'], 'restart': 30, 'newton_rtol': 1e-8,
+                   'discretisation': 'Q1, element-mean coefficient'},
+        'ok': ok32, 'newton_iters': reps32[-1]['newton_iters'], 'krylov_iters': reps32[-1]['linear_iters'],
+        'ge_effective': ge32, 'final_rel_residual': reps32[-1]['fnorm'] / reps32[-1]['fnorm0'],
+        'roofline': roofline, 'kernel_shares': kernel_shares, 'cpu_baseline': cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -1,0 +1,131 @@
+"""ctypes mirrors of include/libjfnk.h and the loader of libjfnk.so."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libjfnk.so')
+
+MAX_LEVELS = 12
+MAX_HIST = 128
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOCONV, E_BREAKDOWN, E_NONFINITE = range(7)
+STATUS = {0: 'ok', 1: 'inval', 2: 'nomem', 3: 'device', 4: 'noconv', 5: 'breakdown', 6: 'nonfinite'}
+BRATU, PLAP, INVCOEF, NEOHOOKE = range(4)
+F64, F32 = 0, 1
+EPS_NORM, EPS_PAPER = 0, 1
+FORCING_RELATIVE, FORCING_PAPER = 0, 1
+MERIT_AUTO, MERIT_RESIDUAL = 0, 1
+TIMER_CHEB_FINE, TIMER_JV_OUTER, TIMER_RESID_FINE, TIMER_ARNOLDI = range(4)
+KINDS = {'bratu': BRATU, 'plap': PLAP, 'invcoef': INVCOEF, 'neohooke': NEOHOOKE}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [('kind', ctypes.c_int), ('dim', ctypes.c_int), ('n', ctypes.c_int * 3),
+                ('h', ctypes.c_double), ('dirichlet', ctypes.c_uint), ('param', ctypes.c_double * 4),
+                ('nlevels', ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [('nu_pre', ctypes.c_int), ('nu_post', ctypes.c_int),
+                ('cheb_lo', ctypes.c_double), ('cheb_hi', ctypes.c_double),
+                ('power_maxit', ctypes.c_int), ('power_fixed', ctypes.c_int), ('power_rtol', ctypes.c_double),
+                ('coarse_maxit', ctypes.c_int), ('coarse_atol', ctypes.c_double),
+                ('coarse_rtol', ctypes.c_double), ('shift_gamma', ctypes.c_double), ('shift_max', ctypes.c_int),
+                ('restart', ctypes.c_int), ('max_cycles', ctypes.c_int), ('newton_maxit', ctypes.c_int),
+                ('newton_rtol', ctypes.c_double), ('newton_atol', ctypes.c_double),
+                ('ls_maxit', ctypes.c_int), ('armijo', ctypes.c_double), ('vcycle_prec', ctypes.c_int),
+                ('eps_mode', ctypes.c_int), ('fd_root', ctypes.c_double), ('forcing', ctypes.c_int),
+                ('merit', ctypes.c_int), ('seed', ctypes.c_ulonglong), ('kernel_path', ctypes.c_int),
+                ('fd_form', ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [('status', ctypes.c_int), ('newton_iters', ctypes.c_int), ('linear_iters', ctypes.c_int),
+                ('fnorm0', ctypes.c_double), ('fnorm', ctypes.c_double), ('nhist', ctypes.c_int),
+                ('fnorm_hist', ctypes.c_double * MAX_HIST), ('alpha_hist', ctypes.c_double * MAX_HIST),
+                ('eta_hist', ctypes.c_double * MAX_HIST), ('lin_hist', ctypes.c_int * MAX_HIST),
+                ('ge_level', ctypes.c_double * MAX_LEVELS), ('ge_effective', ctypes.c_double),
+                ('lambda_', ctypes.c_double * MAX_LEVELS), ('coarse_calls', ctypes.c_longlong),
+                ('coarse_iters', ctypes.c_longlong), ('neg_curv', ctypes.c_int),
+                ('last_shift', ctypes.c_double), ('time_ms', ctypes.c_double)]
+
+    def to_dict(self, nlevels):
+        n = self.nhist
+        return {
+            'status': STATUS.get(self.status, str(self.status)),
+            'newton_iters': self.newton_iters, 'linear_iters': self.linear_iters,
+            'fnorm0': self.fnorm0, 'fnorm': self.fnorm,
+            'fnorm_hist': list(self.fnorm_hist[:n]), 'alpha_hist': list(self.alpha_hist[:n]),
+            'eta_hist': list(self.eta_hist[:n]), 'lin_hist': list(self.lin_hist[:n]),
+            'ge_level': list(self.ge_level[:nlevels]), 'ge_effective': self.ge_effective,
+            'lambda': list(self.lambda_[:nlevels]), 'coarse_calls': self.coarse_calls,
+            'coarse_iters': self.coarse_iters, 'neg_curv': self.neg_curv,
+            'last_shift': self.last_shift, 'time_ms': self.time_ms,
+        }
+
+
+EXPORTS = [
+    'jfnk_default_options', 'jfnk_workspace_bytes', 'jfnk_create', 'jfnk_destroy', 'jfnk_last_error',
+    'jfnk_version', 'jfnk_abi_sizes', 'jfnk_level_info', 'jfnk_residual', 'jfnk_energy', 'jfnk_jv',
+    'mg_project', 'mg_restrict', 'mg_prolong_add', 'mg_setup', 'mg_reset_eigvecs', 'mg_get_level',
+    'mg_get_lambda', 'mg_smooth', 'mg_coarse_solve', 'mg_vcycle', 'jfnk_solve', 'jfnk_vjp',
+    'jfnk_adjoint_solve', 'jfnk_assemble_load', 'jfnk_timer_enable', 'jfnk_timer_read',
+]
+
+_lib = None
+
+
+def load():
+    """Load libjfnk.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f'{LIB_PATH} is not built: run python -m paper_2103_13890_amd.build')
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, c_int, c_dbl, c_size = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    P, O, R = ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Report)
+    sig = {
+        'jfnk_default_options': (None, [O]),
+        'jfnk_workspace_bytes': (c_int, [P, O, ctypes.POINTER(c_size)]),
+        'jfnk_create': (c_int, [P, O, vp, c_size, vp, ctypes.POINTER(vp)]),
+        'jfnk_destroy': (None, [vp]),
+        'jfnk_last_error': (ctypes.c_char_p, [vp]),
+        'jfnk_version': (ctypes.c_char_p, []),
+        'jfnk_abi_sizes': (None, [ctypes.POINTER(c_size)]),
+        'jfnk_level_info': (c_int, [vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_longlong),
+                                    ctypes.POINTER(ctypes.c_longlong)]),
+        'jfnk_residual': (c_int, [vp, c_int, c_int, vp, vp, vp, vp]),
+        'jfnk_energy': (c_int, [vp, c_int, vp, vp, ctypes.POINTER(c_dbl)]),
+        'jfnk_jv': (c_int, [vp, c_int, c_int, vp, vp, vp, vp, c_dbl, vp, ctypes.POINTER(c_dbl)]),
+        'mg_project': (c_int, [vp, c_int, c_int, vp, vp]),
+        'mg_restrict': (c_int, [vp, c_int, c_int, vp, vp]),
+        'mg_prolong_add': (c_int, [vp, c_int, c_int, vp, vp]),
+        'mg_setup': (c_int, [vp, vp, vp]),
+        'mg_reset_eigvecs': (c_int, [vp]),
+        'mg_get_level': (c_int, [vp, c_int, c_int, vp]),
+        'mg_get_lambda': (c_int, [vp, ctypes.POINTER(c_dbl)]),
+        'mg_smooth': (c_int, [vp, c_int, vp, vp, c_int, c_int]),
+        'mg_coarse_solve': (c_int, [vp, vp, vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_int),
+                                    ctypes.POINTER(c_int)]),
+        'mg_vcycle': (c_int, [vp, vp, vp]),
+        'jfnk_solve': (c_int, [vp, vp, vp, vp, R]),
+        'jfnk_vjp': (c_int, [vp, c_int, c_int, vp, vp, vp, vp]),
+        'jfnk_adjoint_solve': (c_int, [vp, vp, vp, vp, c_dbl, vp, R]),
+        'jfnk_assemble_load': (c_int, [vp, c_int, ctypes.POINTER(c_dbl), c_int, vp]),
+        'jfnk_timer_enable': (c_int, [vp, c_int, c_int]),
+        'jfnk_timer_read': (c_int, [vp, c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_dbl)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def abi_sizes():
+    lib = load()
+    out = (ctypes.c_size_t * 3)()
+    lib.jfnk_abi_sizes(out)
+    return tuple(out)

@@ -1,0 +1,117 @@
+// Host-side launch interface of libjfnk's kernels.  Every function queues
+// work on ex.st and returns immediately; slots are device doubles.
+#pragma once
+#include "common.hpp"
+#include "reduce.hpp"
+
+namespace jfnk {
+
+struct FdStep;
+
+struct Exec {
+    hipStream_t st;
+    Red red;
+    int path;            // 0 auto, 1 node-centric, 2 z-marching tiles
+};
+
+// a1 residual: F = A(u) - b (b nullable), A(u) -> Aout (nullable), ||F||^2 -> nrm2 (nullable)
+template <typename T>
+void op_residual(const Exec &, const Grid &, const Phys &, const T *kap, const T *u, const T *b, T *F, T *Aout,
+                 double *nrm2);
+// FD evaluations (Sec. 1) take mode = M_FD_PLAIN ((A(x + eps v) - Ax)/eps
+// with the cached Ax) or M_FD_DIFF (the element difference form; Ax unused).
+// a5 FD Jacobian action
+template <typename T, typename TV>
+void op_jv(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax, const TV *v,
+           const double *num, const double *vn2, double eps_fixed, T *Jv);
+// a6 Chebyshev step with d_k (||d_k||^2 in vn2): s += d; r -= J d; dn = c1 d + c2 r
+template <typename T>
+void op_cheb_step(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
+                  const T *d, const double *num, const double *vn2, T *r, T *s, T *dn, double c1, double c2,
+                  double *dn_nrm2);
+// Chebyshev start from s: r = b - J s, d = r / theta
+template <typename T>
+void op_cheb_init(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
+                  const T *s, const double *num, const double *vn2, const T *b, T *r, T *d, double inv_theta,
+                  double *d_nrm2);
+// a7 residual of the correction: t = b - J s
+template <typename T>
+void op_resid_jv(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
+                 const T *s, const double *num, const double *vn2, const T *b, T *t);
+// a4 power step: q = J v, out[0] = v.q, out[1] = ||q||^2
+template <typename T>
+void op_power(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax, const T *v,
+              const double *num, const double *vn2, T *q, double *out);
+
+// energy Psi_h(u) (element sum) -> out[0]   (FP64, variational kinds)
+void op_energy(const Exec &, const Grid &, const Phys &, const double *u, double *out);
+// exact VJP: out = J(u)^T lam (wrt 0) or (dF/dm)^T lam (wrt 1, kap = e^m)
+void op_vjp(const Exec &, const Grid &, const Phys &, const double *kap, const double *u, const double *lam,
+            int wrt, double *out);
+
+// ---- vectors (n = nodes, nc components, SoA) ---------------------------------
+template <typename T> void vec_fill(const Exec &, T *x, long long n, T val);
+// y = x on DoFs, 0 on Dirichlet nodes; ||y||^2 -> nrm2 (nullable)
+template <typename TI, typename TO>
+void vec_cast(const Exec &, const Grid &, int nc, const TI *x, TO *y, double *nrm2);
+// y = a x on DoFs (0 on Dirichlet); ||y||^2 -> nrm2 (nullable); a = scale * (1/sqrt(*rs) if rs)
+template <typename T>
+void vec_scale(const Exec &, const Grid &, int nc, const T *x, T *y, double scale, const double *rs,
+               double *nrm2);
+// FD step numerator of a level: root (1 + ||x||) (mode 0) or root mean(1 + |x|) (mode 1)
+template <typename T>
+void vec_eps_num(const Exec &, const Grid &, int nc, const T *x, double root, int mode, double *num);
+// Chebyshev start from zero: r = b, d = b / theta, s = 0; ||d||^2
+template <typename T>
+void vec_cheb_zero(const Exec &, const Grid &, int nc, const T *b, T *r, T *d, T *s, double inv_theta,
+                   double *d_nrm2);
+// out = s + d on DoFs; ||out||^2 (out may alias s)
+template <typename T>
+void vec_add(const Exec &, const Grid &, int nc, const T *s, const T *d, T *out, double *nrm2);
+// SplitMix64 start vector of a level, masked; ||v||^2
+template <typename T>
+void vec_random(const Exec &, const Grid &, int nc, unsigned long long seed, int level, T *v, double *nrm2);
+// kap = exp(m) at every node
+template <typename T> void vec_exp(const Exec &, long long n, const double *m, T *kap);
+// sum x.y over n entries -> out
+template <typename TA, typename TB>
+void vec_dot(const Exec &, long long n, const TA *x, const TB *y, double *out);
+
+// Arnoldi (CGS2) on FP64 basis vectors V_0..V_{k-1} spaced by ld:
+// h_j = V_j . w
+void arn_dots(const Exec &, long long n, const double *V, long long ld, int k, const double *w, double *h);
+// w -= sum_j V_j h_j; then h2_j = V_j . w (h2 nullable) or ||w||^2 -> nrm2
+void arn_update(const Exec &, long long n, const double *V, long long ld, int k, const double *h, double *w,
+                double *h2, double *nrm2);
+// x += sum_j y_j Z_j (Z in TZ precision)
+template <typename TZ>
+void arn_combine(const Exec &, long long n, const TZ *Z, long long ld, int k, const double *y, double *x);
+// y = x + a d (FP64)
+void vec_axpy(const Exec &, long long n, const double *x, double a, const double *d, double *y);
+
+// ---- transfers (level l fine, l-1 coarse) -----------------------------------------
+template <typename TI, typename TO>
+void tr_project(const Exec &, const Grid &fine, const Grid &coarse, int nc, const TI *xf, TO *xc);
+template <typename T>
+void tr_restrict(const Exec &, const Grid &fine, const Grid &coarse, int nc, const T *rf, T *rc, double *nrm2);
+template <typename T>
+void tr_prolong_add(const Exec &, const Grid &fine, const Grid &coarse, int nc, const T *cc, T *sf,
+                    double *nrm2);
+
+// ---- coarse solve (Algorithm 1, level 0) ------------------------------------------
+struct CoarseArgs {
+    int maxit, shift_max;
+    double atol, rtol, gamma;
+    double *stats;      // [0] last shift, [1] total CG iterations, [2] rounds, [3] FD evaluations,
+                        // [4] negative-curvature exits (accumulated over calls)
+};
+template <typename T>
+void coarse_solve(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
+                  const double *num, const T *b, T *s, T *work, const CoarseArgs &);
+int coarse_max_nodes();
+
+// ---- loads ---------------------------------------------------------------------------
+void load_gaussians(const Exec &, const Grid &, const double *prm, int count, double *b);
+void load_traction(const Exec &, const Grid &, const double *t, double *b);
+
+}  // namespace jfnk

@@ -1,0 +1,264 @@
+// Evaluation of A(w) = sum_e r_e(w_e) at nodes, and of the finite-difference
+// Jacobian action (Sec. 1), with fused epilogues.  A kernel instance is
+// (grid dimension, residual kind, mode, precision, epilogue):
+//
+//   mode M_RESID    val = A(x)
+//        M_FD_PLAIN val = (A(x + eps v) - A(x)) / eps, A(x) read from a cache
+//        M_FD_DIFF  val = the same quotient summed from per-element
+//                   difference forms (elem_*_fd), no cache read
+//   epilogue        consumes val at node i: store F = val - b, store J v,
+//                   a fused Chebyshev step, a power-method step, ...
+//
+// The step eps = num / ||v|| is read from device scalars at kernel start
+// (num: the level's root (1 + ||x||) or the paper's variant; ||v||^2 written
+// by the kernel that produced v), so no host round trip is needed.  The
+// direction v is taken as 0 on Dirichlet nodes (J acts on the DoF space).
+//
+// This header holds the node-centric form (one thread per node, the
+// elements around it evaluated in registers); stencil_tiled.hpp holds the
+// z-marching LDS-tiled form for large 3D levels.  Both share the element
+// routines and the epilogues.
+#pragma once
+#include "elem.hpp"
+#include "reduce.hpp"
+
+namespace jfnk {
+
+struct FdStep {
+    const double *num;   // numerator slot (nullptr: not an FD evaluation)
+    const double *vn2;   // ||v||^2 slot
+    double fixed;        // > 0: use this step
+    __device__ __forceinline__ double eps() const {
+        if (fixed > 0.0) return fixed;
+        if (num == nullptr) return 0.0;
+        double n2 = *vn2;
+        return n2 > 0.0 ? *num / sqrt(n2) : 0.0;
+    }
+};
+
+// ---- epilogues ---------------------------------------------------------------
+// NS: number of grid sums; NCOMP: components; node(i, val, dir, sums);
+// operator()(totals) runs once in the last block.
+
+// F = val - b (b nullable); Aout (nullable) receives val; ||F||^2 -> out
+template <typename T, int NC> struct EpiResidual {
+    static constexpr int NS = 1;
+    static constexpr int NCOMP = NC;
+    const T *b;
+    T *F;
+    T *Aout;
+    long long nn;
+    double *out;
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *s) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            T f = dir ? T(0) : (b ? val[c] - b[c * nn + i] : val[c]);
+            F[c * nn + i] = f;
+            if (Aout) Aout[c * nn + i] = dir ? T(0) : val[c];
+            s[0] += (double)f * (double)f;
+        }
+    }
+    __device__ void operator()(const double *t) const { if (out) out[0] = t[0]; }
+};
+
+// J v
+template <typename T, int NC> struct EpiJv {
+    static constexpr int NS = 0;
+    static constexpr int NCOMP = NC;
+    T *Jv;
+    long long nn;
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Jv[c * nn + i] = dir ? T(0) : val[c];
+    }
+    __device__ void operator()(const double *) const {}
+};
+
+// Chebyshev step k (three-term recurrence), q = J d_k:
+// s <- s + d_k;  r <- r - q;  d_{k+1} = c1 d_k + c2 r;  ||d_{k+1}||^2 -> out
+template <typename T, int NC> struct EpiCheb {
+    static constexpr int NS = 1;
+    static constexpr int NCOMP = NC;
+    const T *d;
+    T *r, *s, *dn;
+    T c1, c2;
+    long long nn;
+    double *out;
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            if (dir) {
+                r[k] = T(0); s[k] = T(0); dn[k] = T(0);
+                continue;
+            }
+            const T dk = d[k];
+            s[k] = s[k] + dk;
+            const T rk = r[k] - val[c];
+            r[k] = rk;
+            const T dnew = c1 * dk + c2 * rk;
+            dn[k] = dnew;
+            sm[0] += (double)dnew * (double)dnew;
+        }
+    }
+    __device__ void operator()(const double *t) const { out[0] = t[0]; }
+};
+
+// t = b - J s  (the residual restricted in Algorithm 1)
+template <typename T, int NC> struct EpiResidJv {
+    static constexpr int NS = 0;
+    static constexpr int NCOMP = NC;
+    const T *b;
+    T *t;
+    long long nn;
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            t[k] = dir ? T(0) : b[k] - val[c];
+        }
+    }
+    __device__ void operator()(const double *) const {}
+};
+
+// Chebyshev start from s != 0: r = b - J s, d = r / theta; ||d||^2 -> out
+template <typename T, int NC> struct EpiChebInit {
+    static constexpr int NS = 1;
+    static constexpr int NCOMP = NC;
+    const T *b;
+    T *r, *d;
+    T inv_theta;
+    long long nn;
+    double *out;
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            if (dir) { r[k] = T(0); d[k] = T(0); continue; }
+            const T rk = b[k] - val[c];
+            r[k] = rk;
+            const T dk = rk * inv_theta;
+            d[k] = dk;
+            sm[0] += (double)dk * (double)dk;
+        }
+    }
+    __device__ void operator()(const double *t) const { out[0] = t[0]; }
+};
+
+// power step: q = J v; v.q and ||q||^2 -> out[0..1]
+template <typename T, int NC> struct EpiPower {
+    static constexpr int NS = 2;
+    static constexpr int NCOMP = NC;
+    const T *v;
+    T *q;
+    long long nn;
+    double *out;
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            const T qk = dir ? T(0) : val[c];
+            q[k] = qk;
+            sm[0] += (double)v[k] * (double)qk;
+            sm[1] += (double)qk * (double)qk;
+        }
+    }
+    __device__ void operator()(const double *t) const { out[0] = t[0]; out[1] = t[1]; }
+};
+
+// ---- one element in any mode ------------------------------------------------------
+// xe: state corners; ve: direction corners (FD modes); r: output contributions
+template <int DIM, int KIND, int MODE, typename T, int NC, int NV>
+__device__ __forceinline__ void elem_eval(const T (*xe)[NV], const T (*ve)[NV], const T *kp, T eps,
+                                          const Phys &ph, T h, T (*r)[NV]) {
+    if constexpr (KIND == JFNK_NEOHOOKE) {
+        if constexpr (MODE == M_FD_DIFF) {
+            elem_neohooke_fd<T>(xe, ve, eps, ph, h, r);
+        } else if constexpr (MODE == M_FD_PLAIN) {
+            T w[3][8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int a = 0; a < 8; ++a) w[c][a] = xe[c][a] + eps * ve[c][a];
+            elem_neohooke<T>(w, ph, h, r);
+        } else {
+            elem_neohooke<T>(xe, ph, h, r);
+        }
+    } else {
+        if constexpr (MODE == M_FD_DIFF) {
+            elem_scalar_fd<DIM, KIND, T>(xe[0], ve[0], kp, eps, ph, h, r[0]);
+        } else if constexpr (MODE == M_FD_PLAIN) {
+            T w[NV];
+#pragma unroll
+            for (int a = 0; a < NV; ++a) w[a] = xe[0][a] + eps * ve[0][a];
+            elem_scalar<DIM, KIND, T>(w, kp, ph, h, r[0]);
+        } else {
+            elem_scalar<DIM, KIND, T>(xe[0], kp, ph, h, r[0]);
+        }
+    }
+}
+
+// ---- node-centric value ---------------------------------------------------------------
+// Sum of the contributions of the elements around node (X, Y, Z).
+template <int DIM, int KIND, int MODE, typename T, typename TV>
+__device__ __forceinline__ void node_value(const Grid &g, const Phys &ph, const T *kap, const T *x, const TV *v,
+                                           const T *Ax, double eps, int X, int Y, int Z, long long i, T *val) {
+    constexpr int NV = Cell<DIM>::NV;
+    constexpr int NC = (KIND == JFNK_NEOHOOKE) ? 3 : 1;
+    const long long nn = g.nn;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) val[c] = T(0);
+    if (MODE != M_RESID && eps == 0.0) return;
+    const T h = (T)g.h;
+    const T e = (T)eps;
+    for (int el = 0; el < NV; ++el) {
+        const int ex = X - (el & 1), ey = Y - ((el >> 1) & 1), ez = (DIM == 3) ? Z - ((el >> 2) & 1) : 0;
+        if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny) continue;
+        if (DIM == 3 && (ez < 0 || ez >= g.nz)) continue;
+        T xe[NC][NV], ve[NC][NV], kp[NV], r[NC][NV];
+#pragma unroll
+        for (int a = 0; a < NV; ++a) {
+            const int ax = ex + (a & 1), ay = ey + ((a >> 1) & 1), az = ez + ((a >> 2) & 1);
+            const long long j = node_index(g, ax, ay, az);
+            const bool dj = (MODE != M_RESID) && is_dirichlet(g, ax, ay, az);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                xe[c][a] = x[c * nn + j];
+                ve[c][a] = (MODE == M_RESID || dj) ? T(0) : (T)v[c * nn + j];
+            }
+            kp[a] = (KIND == JFNK_INVCOEF) ? kap[j] : T(0);
+        }
+        elem_eval<DIM, KIND, MODE, T, NC, NV>(xe, ve, kp, e, ph, h, r);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) val[c] += r[c][el];
+    }
+    if constexpr (MODE == M_FD_PLAIN) {
+        const T ie = (T)(1.0 / eps);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) val[c] = (val[c] - Ax[c * nn + i]) * ie;
+    }
+}
+
+template <int DIM, int KIND, int MODE, typename T, typename TV, class Epi>
+__global__ __launch_bounds__(BLOCK) void k_node(Grid g, Phys ph, const T *kap, const T *x, const TV *v, const T *Ax,
+                                                FdStep fd, Epi epi, Red red) {
+    constexpr int NC = (KIND == JFNK_NEOHOOKE) ? 3 : 1;
+    const double eps = fd.eps();
+    double sums[Epi::NS > 0 ? Epi::NS : 1];
+#pragma unroll
+    for (int k = 0; k < (Epi::NS > 0 ? Epi::NS : 1); ++k) sums[k] = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += stride) {
+        int X, Y, Z;
+        node_coords(g, i, X, Y, Z);
+        const bool dir = is_dirichlet(g, X, Y, Z);
+        T val[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) val[c] = T(0);
+        if (!dir) node_value<DIM, KIND, MODE, T, TV>(g, ph, kap, x, v, Ax, eps, X, Y, Z, i, val);
+        epi.node(i, val, dir, sums);
+    }
+    if constexpr (Epi::NS > 0) grid_sum<Epi::NS>(sums, red, epi);
+}
+
+}  // namespace jfnk

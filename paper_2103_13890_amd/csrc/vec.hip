@@ -1,0 +1,496 @@
+// Vector kernels: masked casts and scalings with fused norms, Chebyshev
+// start/finish, FD-step numerators, SplitMix64 start vectors, Gram-Schmidt
+// passes of flexible GMRES, and load-vector assembly.
+#include "elem.hpp"
+#include "ops.hpp"
+
+namespace jfnk {
+
+static inline int vblocks(long long n, int cap = 2048) {
+    long long b = (n + BLOCK - 1) / BLOCK;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+__device__ __forceinline__ bool dir_at(const Grid &g, long long i) {
+    int x, y, z;
+    node_coords(g, i, x, y, z);
+    return is_dirichlet(g, x, y, z);
+}
+
+#define GRID_STRIDE(i, n) \
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+// ---------------------------------------------------------------------------
+template <typename T> __global__ void k_fill(T *x, long long n, T v) {
+    GRID_STRIDE(i, n) x[i] = v;
+}
+template <typename T> void vec_fill(const Exec &ex, T *x, long long n, T val) {
+    k_fill<T><<<vblocks(n), BLOCK, 0, ex.st>>>(x, n, val);
+}
+template void vec_fill<float>(const Exec &, float *, long long, float);
+template void vec_fill<double>(const Exec &, double *, long long, double);
+
+// y = a x on DoFs; a = scale (* 1/sqrt(*rs))
+template <typename TI, typename TO>
+__global__ void k_scale(Grid g, int nc, const TI *x, TO *y, double scale, const double *rs, Red red, double *out) {
+    double a = scale;
+    if (rs) a = (*rs > 0.0) ? scale / sqrt(*rs) : 0.0;
+    double s[1] = {0.0};
+    GRID_STRIDE(i, g.nn) {
+        const bool d = dir_at(g, i);
+        for (int c = 0; c < nc; ++c) {
+            const long long k = c * g.nn + i;
+            TO v = d ? TO(0) : (TO)(a * (double)x[k]);
+            y[k] = v;
+            s[0] += (double)v * (double)v;
+        }
+    }
+    if (out) grid_sum<1>(s, red, FinStore<1>{out});
+}
+
+template <typename TI, typename TO>
+void vec_cast(const Exec &ex, const Grid &g, int nc, const TI *x, TO *y, double *nrm2) {
+    k_scale<TI, TO><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, x, y, 1.0, nullptr, ex.red, nrm2);
+}
+template void vec_cast<double, double>(const Exec &, const Grid &, int, const double *, double *, double *);
+template void vec_cast<double, float>(const Exec &, const Grid &, int, const double *, float *, double *);
+template void vec_cast<float, double>(const Exec &, const Grid &, int, const float *, double *, double *);
+template void vec_cast<float, float>(const Exec &, const Grid &, int, const float *, float *, double *);
+
+template <typename T>
+void vec_scale(const Exec &ex, const Grid &g, int nc, const T *x, T *y, double scale, const double *rs,
+               double *nrm2) {
+    k_scale<T, T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, x, y, scale, rs, ex.red, nrm2);
+}
+template void vec_scale<float>(const Exec &, const Grid &, int, const float *, float *, double, const double *, double *);
+template void vec_scale<double>(const Exec &, const Grid &, int, const double *, double *, double, const double *, double *);
+
+// FD step numerator (Sec. 1): mode 0 root (1 + ||x||), mode 1 root mean(1 + |x_i|)
+struct FinEpsNum {
+    double *out;
+    double root, ndof;
+    int mode;
+    __device__ void operator()(const double *t) const {
+        out[0] = mode == 0 ? root * (1.0 + sqrt(t[0])) : root * ((ndof + t[1]) / ndof);
+    }
+};
+template <typename T>
+__global__ void k_eps_num(Grid g, int nc, const T *x, Red red, FinEpsNum fin) {
+    double s[2] = {0.0, 0.0};
+    GRID_STRIDE(i, g.nn) {
+        if (dir_at(g, i)) continue;
+        for (int c = 0; c < nc; ++c) {
+            const double v = (double)x[c * g.nn + i];
+            s[0] += v * v;
+            s[1] += fabs(v);
+        }
+    }
+    grid_sum<2>(s, red, fin);
+}
+static double count_dofs(const Grid &g, int nc) {
+    // DoFs = nodes off the Dirichlet faces
+    long long nx = g.NX, ny = g.NY, nz = g.NZ;
+    if (g.dir & JFNK_FACE_XLO) nx--;
+    if (g.dir & JFNK_FACE_XHI) nx--;
+    if (g.dir & JFNK_FACE_YLO) ny--;
+    if (g.dir & JFNK_FACE_YHI) ny--;
+    if (g.dim == 3) {
+        if (g.dir & JFNK_FACE_ZLO) nz--;
+        if (g.dir & JFNK_FACE_ZHI) nz--;
+    }
+    long long n = (nx > 0 ? nx : 0) * (ny > 0 ? ny : 0) * (nz > 0 ? nz : 0);
+    return (double)n * nc;
+}
+template <typename T>
+void vec_eps_num(const Exec &ex, const Grid &g, int nc, const T *x, double root, int mode, double *num) {
+    double nd = count_dofs(g, nc);
+    k_eps_num<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, x, ex.red, FinEpsNum{num, root, nd > 0 ? nd : 1.0, mode});
+}
+template void vec_eps_num<float>(const Exec &, const Grid &, int, const float *, double, int, double *);
+template void vec_eps_num<double>(const Exec &, const Grid &, int, const double *, double, int, double *);
+
+// Chebyshev from s = 0: r = b, d = b / theta, s = 0
+template <typename T>
+__global__ void k_cheb_zero(Grid g, int nc, const T *b, T *r, T *d, T *s, T inv_theta, Red red, double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, g.nn) {
+        const bool dd = dir_at(g, i);
+        for (int c = 0; c < nc; ++c) {
+            const long long k = c * g.nn + i;
+            T bk = dd ? T(0) : b[k];
+            r[k] = bk;
+            T dk = bk * inv_theta;
+            d[k] = dk;
+            s[k] = T(0);
+            sm[0] += (double)dk * (double)dk;
+        }
+    }
+    grid_sum<1>(sm, red, FinStore<1>{out});
+}
+template <typename T>
+void vec_cheb_zero(const Exec &ex, const Grid &g, int nc, const T *b, T *r, T *d, T *s, double inv_theta,
+                   double *d_nrm2) {
+    k_cheb_zero<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, b, r, d, s, (T)inv_theta, ex.red, d_nrm2);
+}
+template void vec_cheb_zero<float>(const Exec &, const Grid &, int, const float *, float *, float *, float *, double, double *);
+template void vec_cheb_zero<double>(const Exec &, const Grid &, int, const double *, double *, double *, double *, double, double *);
+
+template <typename T>
+__global__ void k_add(Grid g, int nc, const T *s, const T *d, T *o, Red red, double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, g.nn) {
+        const bool dd = dir_at(g, i);
+        for (int c = 0; c < nc; ++c) {
+            const long long k = c * g.nn + i;
+            T v = dd ? T(0) : s[k] + d[k];
+            o[k] = v;
+            sm[0] += (double)v * (double)v;
+        }
+    }
+    if (out) grid_sum<1>(sm, red, FinStore<1>{out});
+}
+template <typename T>
+void vec_add(const Exec &ex, const Grid &g, int nc, const T *s, const T *d, T *o, double *nrm2) {
+    k_add<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, s, d, o, ex.red, nrm2);
+}
+template void vec_add<float>(const Exec &, const Grid &, int, const float *, const float *, float *, double *);
+template void vec_add<double>(const Exec &, const Grid &, int, const double *, const double *, double *, double *);
+
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator: value
+// at flat index k of level l is the (k+1)-th output of the sequence whose
+// state starts at seed + l 2^32, mapped to [-1, 1).
+__device__ __forceinline__ double splitmix_uniform(unsigned long long s0, unsigned long long k) {
+    unsigned long long z = s0 + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+template <typename T>
+__global__ void k_random(Grid g, int nc, unsigned long long s0, T *v, Red red, double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, g.nn) {
+        const bool dd = dir_at(g, i);
+        for (int c = 0; c < nc; ++c) {
+            const long long k = c * g.nn + i;
+            T val = dd ? T(0) : (T)splitmix_uniform(s0, (unsigned long long)k);
+            v[k] = val;
+            sm[0] += (double)val * (double)val;
+        }
+    }
+    grid_sum<1>(sm, red, FinStore<1>{out});
+}
+template <typename T>
+void vec_random(const Exec &ex, const Grid &g, int nc, unsigned long long seed, int level, T *v, double *nrm2) {
+    unsigned long long s0 = seed + ((unsigned long long)level << 32);
+    k_random<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, s0, v, ex.red, nrm2);
+}
+template void vec_random<float>(const Exec &, const Grid &, int, unsigned long long, int, float *, double *);
+template void vec_random<double>(const Exec &, const Grid &, int, unsigned long long, int, double *, double *);
+
+template <typename T> __global__ void k_exp(long long n, const double *m, T *kap) {
+    GRID_STRIDE(i, n) kap[i] = (T)exp(m[i]);
+}
+template <typename T> void vec_exp(const Exec &ex, long long n, const double *m, T *kap) {
+    k_exp<T><<<vblocks(n), BLOCK, 0, ex.st>>>(n, m, kap);
+}
+template void vec_exp<float>(const Exec &, long long, const double *, float *);
+template void vec_exp<double>(const Exec &, long long, const double *, double *);
+
+template <typename TA, typename TB>
+__global__ void k_dot(long long n, const TA *x, const TB *y, Red red, double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, n) sm[0] += (double)x[i] * (double)y[i];
+    grid_sum<1>(sm, red, FinStore<1>{out});
+}
+template <typename TA, typename TB>
+void vec_dot(const Exec &ex, long long n, const TA *x, const TB *y, double *out) {
+    k_dot<TA, TB><<<vblocks(n), BLOCK, 0, ex.st>>>(n, x, y, ex.red, out);
+}
+template void vec_dot<double, double>(const Exec &, long long, const double *, const double *, double *);
+template void vec_dot<float, float>(const Exec &, long long, const float *, const float *, double *);
+
+__global__ void k_axpy(long long n, const double *x, double a, const double *d, double *y) {
+    GRID_STRIDE(i, n) y[i] = x[i] + a * d[i];
+}
+void vec_axpy(const Exec &ex, long long n, const double *x, double a, const double *d, double *y) {
+    k_axpy<<<vblocks(n), BLOCK, 0, ex.st>>>(n, x, a, d, y);
+}
+
+// ---- Gram-Schmidt passes ----------------------------------------------------------
+constexpr int ARN_MAX = 32;
+
+struct FinStoreK {
+    double *out;
+    int k;
+    __device__ void operator()(const double *t) const {
+        for (int j = 0; j < k; ++j) out[j] = t[j];
+    }
+};
+
+__global__ __launch_bounds__(BLOCK) void k_arn_dots(long long n, const double *V, long long ld, int k,
+                                                    const double *w, Red red, double *h) {
+    double s[ARN_MAX];
+#pragma unroll
+    for (int j = 0; j < ARN_MAX; ++j) s[j] = 0.0;
+    GRID_STRIDE(i, n) {
+        const double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < ARN_MAX; ++j)
+            if (j < k) s[j] += V[j * ld + i] * wi;
+    }
+    grid_sum<ARN_MAX>(s, red, FinStoreK{h, k});
+}
+void arn_dots(const Exec &ex, long long n, const double *V, long long ld, int k, const double *w, double *h) {
+    k_arn_dots<<<vblocks(n, 1024), BLOCK, 0, ex.st>>>(n, V, ld, k, w, ex.red, h);
+}
+
+// w -= sum_j V_j h_j; then h2 = V^T w (h2 != nullptr) or ||w||^2 -> nrm2
+__global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double *V, long long ld, int k,
+                                                      const double *h, double *w, double *h2, double *nrm2,
+                                                      Red red) {
+    __shared__ double hs[ARN_MAX];
+    if (threadIdx.x < ARN_MAX) hs[threadIdx.x] = threadIdx.x < (unsigned)k ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+    double s[ARN_MAX];
+#pragma unroll
+    for (int j = 0; j < ARN_MAX; ++j) s[j] = 0.0;
+    GRID_STRIDE(i, n) {
+        double wi = w[i];
+        double vj[ARN_MAX];
+#pragma unroll
+        for (int j = 0; j < ARN_MAX; ++j)
+            if (j < k) {
+                vj[j] = V[j * ld + i];
+                wi -= hs[j] * vj[j];
+            }
+        w[i] = wi;
+        if (h2) {
+#pragma unroll
+            for (int j = 0; j < ARN_MAX; ++j)
+                if (j < k) s[j] += vj[j] * wi;
+        } else {
+            s[0] += wi * wi;
+        }
+    }
+    if (h2) grid_sum<ARN_MAX>(s, red, FinStoreK{h2, k});
+    else grid_sum<ARN_MAX>(s, red, FinStoreK{nrm2, 1});
+}
+void arn_update(const Exec &ex, long long n, const double *V, long long ld, int k, const double *h, double *w,
+                double *h2, double *nrm2) {
+    k_arn_update<<<vblocks(n, 1024), BLOCK, 0, ex.st>>>(n, V, ld, k, h, w, h2, nrm2, ex.red);
+}
+
+struct CombineArgs {
+    double y[ARN_MAX];
+};
+template <typename TZ>
+__global__ __launch_bounds__(BLOCK) void k_arn_combine(long long n, const TZ *Z, long long ld, int k,
+                                                       CombineArgs ya, double *x) {
+    GRID_STRIDE(i, n) {
+        double acc = x[i];
+        for (int j = 0; j < k; ++j) acc += ya.y[j] * (double)Z[j * ld + i];
+        x[i] = acc;
+    }
+}
+template <typename TZ>
+void arn_combine(const Exec &ex, long long n, const TZ *Z, long long ld, int k, const double *y, double *x) {
+    CombineArgs a;
+    for (int j = 0; j < ARN_MAX; ++j) a.y[j] = j < k ? y[j] : 0.0;
+    k_arn_combine<TZ><<<vblocks(n), BLOCK, 0, ex.st>>>(n, Z, ld, k, a, x);
+}
+template void arn_combine<float>(const Exec &, long long, const float *, long long, int, const double *, double *);
+template void arn_combine<double>(const Exec &, long long, const double *, long long, int, const double *, double *);
+
+// ---- transfers (Sec. 2) ------------------------------------------------------------
+// 1D weights of I^T: fine index f contributes to coarse c with 1 (f = 2c) or
+// 1/2 (f = 2c +- 1).
+template <typename TI, typename TO>
+__global__ void k_project(Grid gf, Grid gc, int nc, const TI *xf, TO *xc) {
+    GRID_STRIDE(i, gc.nn) {
+        int cx, cy, cz;
+        node_coords(gc, i, cx, cy, cz);
+        if (is_dirichlet(gc, cx, cy, cz)) {
+            const long long j = node_index(gf, 2 * cx, 2 * cy, 2 * cz);
+            for (int c = 0; c < nc; ++c) xc[c * gc.nn + i] = (TO)xf[c * gf.nn + j];
+            continue;
+        }
+        const int zlo = gc.dim == 3 ? -1 : 0, zhi = gc.dim == 3 ? 1 : 0;
+        for (int c = 0; c < nc; ++c) {
+            double acc = 0.0, wsum = 0.0;
+            for (int dz = zlo; dz <= zhi; ++dz) {
+                const int fz = 2 * cz + dz;
+                if (fz < 0 || fz >= gf.NZ) continue;
+                const double wz = dz == 0 ? 1.0 : 0.5;
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int fy = 2 * cy + dy;
+                    if (fy < 0 || fy >= gf.NY) continue;
+                    const double wy = wz * (dy == 0 ? 1.0 : 0.5);
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int fx = 2 * cx + dx;
+                        if (fx < 0 || fx >= gf.NX) continue;
+                        const double w = wy * (dx == 0 ? 1.0 : 0.5);
+                        acc += w * (double)xf[c * gf.nn + node_index(gf, fx, fy, fz)];
+                        wsum += w;
+                    }
+                }
+            }
+            xc[c * gc.nn + i] = (TO)(acc / wsum);
+        }
+    }
+}
+template <typename TI, typename TO>
+void tr_project(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const TI *xf, TO *xc) {
+    k_project<TI, TO><<<vblocks(gc.nn), BLOCK, 0, ex.st>>>(gf, gc, nc, xf, xc);
+}
+template void tr_project<double, double>(const Exec &, const Grid &, const Grid &, int, const double *, double *);
+template void tr_project<double, float>(const Exec &, const Grid &, const Grid &, int, const double *, float *);
+template void tr_project<float, float>(const Exec &, const Grid &, const Grid &, int, const float *, float *);
+
+// R = I^T with zero rows at coarse Dirichlet nodes
+template <typename T>
+__global__ void k_restrict(Grid gf, Grid gc, int nc, const T *rf, T *rc, Red red, double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, gc.nn) {
+        int cx, cy, cz;
+        node_coords(gc, i, cx, cy, cz);
+        const bool dd = is_dirichlet(gc, cx, cy, cz);
+        const int zlo = gc.dim == 3 ? -1 : 0, zhi = gc.dim == 3 ? 1 : 0;
+        for (int c = 0; c < nc; ++c) {
+            T acc = T(0);
+            if (!dd) {
+                for (int dz = zlo; dz <= zhi; ++dz) {
+                    const int fz = 2 * cz + dz;
+                    if (fz < 0 || fz >= gf.NZ) continue;
+                    const T wz = dz == 0 ? T(1) : T(0.5);
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const int fy = 2 * cy + dy;
+                        if (fy < 0 || fy >= gf.NY) continue;
+                        const T wy = wz * (dy == 0 ? T(1) : T(0.5));
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int fx = 2 * cx + dx;
+                            if (fx < 0 || fx >= gf.NX) continue;
+                            acc += wy * (dx == 0 ? T(1) : T(0.5)) * rf[c * gf.nn + node_index(gf, fx, fy, fz)];
+                        }
+                    }
+                }
+            }
+            rc[c * gc.nn + i] = acc;
+            sm[0] += (double)acc * (double)acc;
+        }
+    }
+    if (out) grid_sum<1>(sm, red, FinStore<1>{out});
+}
+template <typename T>
+void tr_restrict(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *rf, T *rc, double *nrm2) {
+    k_restrict<T><<<vblocks(gc.nn), BLOCK, 0, ex.st>>>(gf, gc, nc, rf, rc, ex.red, nrm2);
+}
+template void tr_restrict<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
+template void tr_restrict<double>(const Exec &, const Grid &, const Grid &, int, const double *, double *, double *);
+
+// s_f += I c: even fine index -> coarse f/2 (weight 1), odd -> both neighbours (1/2)
+template <typename T>
+__global__ void k_prolong_add(Grid gf, Grid gc, int nc, const T *cc, T *sf, Red red, double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, gf.nn) {
+        int fx, fy, fz;
+        node_coords(gf, i, fx, fy, fz);
+        const bool dd = is_dirichlet(gf, fx, fy, fz);
+        const int x0 = fx >> 1, x1 = (fx + 1) >> 1, y0 = fy >> 1, y1 = (fy + 1) >> 1;
+        const int z0 = fz >> 1, z1 = (fz + 1) >> 1;
+        const T wx = (fx & 1) ? T(0.5) : T(1), wy = (fy & 1) ? T(0.5) : T(1), wz = (fz & 1) ? T(0.5) : T(1);
+        for (int c = 0; c < nc; ++c) {
+            const long long k = c * gf.nn + i;
+            if (dd) {
+                sf[k] = T(0);
+                continue;
+            }
+            const T *cb = cc + c * gc.nn;
+            T v = T(0);
+            // (x0,x1) coincide for even fx: count the node once with weight 1
+            const int nxs = (fx & 1) ? 2 : 1, nys = (fy & 1) ? 2 : 1, nzs = (gf.dim == 3 && (fz & 1)) ? 2 : 1;
+            for (int a = 0; a < nzs; ++a)
+                for (int b = 0; b < nys; ++b)
+                    for (int d = 0; d < nxs; ++d) {
+                        const int X = d ? x1 : x0, Y = b ? y1 : y0, Z = a ? z1 : z0;
+                        v += wx * wy * wz * cb[node_index(gc, X, Y, Z)];
+                    }
+            T s = sf[k] + v;
+            sf[k] = s;
+            sm[0] += (double)s * (double)s;
+        }
+    }
+    if (out) grid_sum<1>(sm, red, FinStore<1>{out});
+}
+template <typename T>
+void tr_prolong_add(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *cc, T *sf, double *nrm2) {
+    k_prolong_add<T><<<vblocks(gf.nn), BLOCK, 0, ex.st>>>(gf, gc, nc, cc, sf, ex.red, nrm2);
+}
+template void tr_prolong_add<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
+template void tr_prolong_add<double>(const Exec &, const Grid &, const Grid &, int, const double *, double *, double *);
+
+// ---- loads ---------------------------------------------------------------------------
+// b_i = sum over adjacent elements e, Gauss points q: w_q f(x_q) phi_i(x_q)
+__global__ void k_load_gauss(Grid g, const double *prm, int count, double *b) {
+    const int D = g.dim;
+    const int NV = 1 << D;
+    const double vol = D == 3 ? g.h * g.h * g.h : g.h * g.h;
+    GRID_STRIDE(i, g.nn) {
+        int x, y, z;
+        node_coords(g, i, x, y, z);
+        if (is_dirichlet(g, x, y, z)) {
+            b[i] = 0.0;
+            continue;
+        }
+        double acc = 0.0;
+        for (int e = 0; e < NV; ++e) {
+            const int ex = x - (e & 1), ey = y - ((e >> 1) & 1), ez = D == 3 ? z - ((e >> 2) & 1) : 0;
+            if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || (D == 3 && (ez < 0 || ez >= g.nz))) continue;
+            for (int q = 0; q < NV; ++q) {
+                double xq[3];
+                xq[0] = (ex + ((q & 1) ? GL1 : GL0)) * g.h;
+                xq[1] = (ey + (((q >> 1) & 1) ? GL1 : GL0)) * g.h;
+                xq[2] = (ez + (((q >> 2) & 1) ? GL1 : GL0)) * g.h;
+                double f = 0.0;
+                for (int k = 0; k < count; ++k) {
+                    const double *pk = prm + k * (D + 2);
+                    double r2 = 0.0;
+                    for (int a = 0; a < D; ++a) r2 += (xq[a] - pk[a]) * (xq[a] - pk[a]);
+                    const double wd = pk[D];
+                    f += pk[D + 1] * exp(-r2 / (2.0 * wd * wd));
+                }
+                // phi at corner e (local index of node i) evaluated at q
+                int c = __builtin_popcount((unsigned)(e ^ q));
+                double ph = 1.0;
+                for (int a = 0; a < D; ++a) ph *= (a < D - c) ? GL1 : GL0;
+                acc += vol / NV * f * ph;
+            }
+        }
+        b[i] = acc;
+    }
+}
+void load_gaussians(const Exec &ex, const Grid &g, const double *prm, int count, double *b) {
+    k_load_gauss<<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, prm, count, b);
+}
+
+// traction t on the x = x_max face: each face cell gives t h^2 / 4 to its corners
+__global__ void k_load_traction(Grid g, double tx, double ty, double tz, double *b) {
+    GRID_STRIDE(i, g.nn) {
+        int x, y, z;
+        node_coords(g, i, x, y, z);
+        double w = 0.0;
+        if (x == g.nx && !is_dirichlet(g, x, y, z)) {
+            const int cy = (y > 0) + (y < g.ny), cz = (z > 0) + (z < g.nz);
+            w = g.h * g.h / 4.0 * cy * cz;
+        }
+        b[i] = w * tx;
+        b[g.nn + i] = w * ty;
+        b[2 * g.nn + i] = w * tz;
+    }
+}
+void load_traction(const Exec &ex, const Grid &g, const double *t, double *b) {
+    k_load_traction<<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, t[0], t[1], t[2], b);
+}
+
+}  // namespace jfnk

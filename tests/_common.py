@@ -1,0 +1,77 @@
+"""Helpers shared by the GPU parity tests: build the same problem for the
+oracle (NumPy) and for libjfnk (through its C ABI) from one preset."""
+import numpy as np
+
+from oracle.fe import Grid
+from oracle.mg import MGOptions
+from oracle.problems import Problem
+from paper_2103_13890_amd import workloads as W
+
+PARAM_NAMES = {'bratu': ('lam',), 'plap': ('p', 'delta'), 'invcoef': (), 'neohooke': ('E', 'nu')}
+
+
+def oracle_problem(w):
+    return Problem(w['kind'], dict(zip(PARAM_NAMES[w['kind']], w['params'])))
+
+
+def oracle_grid(w):
+    return Grid(w['n'], w['h'], w['faces'])
+
+
+def oracle_mg_options(w, **over):
+    o = w['options']
+    kw = dict(nu_pre=o.get('nu_pre', 4), nu_post=o.get('nu_post', 4),
+              power_fixed=bool(o.get('power_fixed', 0)), power_maxit=o.get('power_maxit', 30),
+              coarse_rtol=o.get('coarse_rtol', 1e-6))
+    kw.update(over)
+    return MGOptions(**kw)
+
+
+def make_ctx(w, **opt_over):
+    from paper_2103_13890_amd import api
+    o = dict(w['options'])
+    o.update(opt_over)
+    prob = api.make_problem(w['kind'], w['n'], w['h'], w['faces'], w['params'], w['nlevels'])
+    return api.Context(prob, api.default_options(**o))
+
+
+def ncomp(w):
+    return 3 if w['kind'] == 'neohooke' else 1
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b.ravel())
+    return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
+
+
+def to_dev(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def to_np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def small(kind):
+    """Ragged small grids (x extents not multiples of 64) with several levels."""
+    if kind == 'bratu2d':
+        return W.scaled('bratu2d-32', (36, 20), nlevels=3)
+    if kind == 'bratu3d':
+        w = W.scaled('plap3d-128', (20, 12, 12), nlevels=2)
+        w.update(kind='bratu', params=(2.0,))
+        return w
+    if kind == 'plap':
+        return W.scaled('plap3d-128', (36, 20, 12), nlevels=3, vcycle_prec=0, coarse_rtol=1e-6)
+    if kind == 'invcoef':
+        return W.scaled('invcoef3d-128', (36, 20, 12), nlevels=3)
+    if kind == 'neohooke':
+        return W.scaled('neohooke-256x64', (36, 12, 12), nlevels=3, vcycle_prec=0, coarse_rtol=1e-6)
+    if kind == 'neohooke-solve':
+        return W.scaled('neohooke-256x64', (16, 4, 4), nlevels=3, vcycle_prec=0, coarse_rtol=1e-6)
+    raise KeyError(kind)
