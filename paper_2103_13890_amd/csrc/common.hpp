@@ -14,9 +14,10 @@ struct Grid {
     int dim;
     int nx, ny, nz;        // elements per axis (nz = 0 in 2D)
     int NX, NY, NZ;        // nodes per axis
-    long long nn;          // nodes
+    long long nn;          // nodes (< 2^31, checked at context creation)
     double h;              // element edge
     unsigned dir;          // Dirichlet faces (JFNK_FACE_* bits)
+    double rNX, rNY;       // 1/NX, 1/NY for index decoding
 };
 
 // Residual kind and its constants (Sec. 3 problem statements).
@@ -37,11 +38,25 @@ __host__ __device__ inline long long node_index(const Grid &g, int x, int y, int
     return ((long long)z * g.NY + y) * g.NX + x;
 }
 
-__device__ inline void node_coords(const Grid &g, long long i, int &x, int &y, int &z) {
-    long long q = i / g.NX;
-    x = (int)(i - q * g.NX);
-    z = (int)(q / g.NY);
-    y = (int)(q - (long long)z * g.NY);
+// (x, y, z) of node i.  The quotients come from a double-precision
+// reciprocal: for i < 2^31 its error is below 2^-21, so the truncated
+// quotient is off by at most one and a single correction makes it exact
+// (64-bit integer division has no hardware instruction and costs ~10x more).
+__device__ __forceinline__ void udivmod(unsigned n, unsigned d, double rd, unsigned &q, unsigned &r) {
+    q = (unsigned)((double)n * rd);
+    int rr = (int)(n - q * d);
+    if (rr < 0) { --q; rr += (int)d; }
+    else if (rr >= (int)d) { ++q; rr -= (int)d; }
+    r = (unsigned)rr;
+}
+
+__device__ __forceinline__ void node_coords(const Grid &g, long long i, int &x, int &y, int &z) {
+    unsigned q, r, q2, r2;
+    udivmod((unsigned)i, (unsigned)g.NX, g.rNX, q, r);
+    udivmod(q, (unsigned)g.NY, g.rNY, q2, r2);
+    x = (int)r;
+    y = (int)r2;
+    z = (int)q2;
 }
 
 // Evaluation modes of the stencil kernels: the residual A(x), the FD

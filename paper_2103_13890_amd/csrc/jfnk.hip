@@ -55,7 +55,6 @@ struct jfnk_ctx {
     hipStream_t st = nullptr;
     Exec ex;
     double *scal = nullptr, *part = nullptr;
-    unsigned *cnt = nullptr;
     // finest level, FP64
     long long nn = 0, n = 0;
     double *u = nullptr, *ut = nullptr, *Au = nullptr, *Aut = nullptr, *F = nullptr, *Ft = nullptr;
@@ -101,6 +100,8 @@ Grid level_grid(const jfnk_problem &p, int l) {
     g.nn = (long long)g.NX * g.NY * g.NZ;
     g.h = p.h * (double)(1LL << sh);
     g.dir = p.dirichlet;
+    g.rNX = 1.0 / g.NX;
+    g.rNY = 1.0 / g.NY;
     return g;
 }
 
@@ -165,7 +166,6 @@ void plan(jfnk_ctx *c, Carve &cv) {
     const size_t es = esize(c->vprec);
     c->scal = (double *)cv.take(NSLOT * sizeof(double));
     c->part = (double *)cv.take(PART_CAP * sizeof(double));
-    c->cnt = (unsigned *)cv.take(256);
     for (int l = 0; l < c->prob.nlevels; ++l) {
         Level &L = c->lev[l];
         L.g = level_grid(c->prob, l);
@@ -245,19 +245,26 @@ struct TimeScope {
     jfnk_ctx *c;
     TimerRec *t;
     size_t k;
-    TimeScope(jfnk_ctx *c_, int which) : c(c_), t(nullptr), k(0) {
+    // main_only: the end event is taken right after the stencil kernel,
+    // before its reduction finish (see Exec::mark_main_end); otherwise at
+    // the end of the scope
+    TimeScope(jfnk_ctx *c_, int which, bool main_only = true) : c(c_), t(nullptr), k(0), main(main_only) {
         if (which >= 0 && which < JFNK_TIMER_COUNT) t = &c_->timers[which];
         if (t && t->on && t->used + 2 <= t->ev.size()) {
             k = t->used;
             t->used += 2;
             (void)hipEventRecord(t->ev[k], c->st);
+            if (main) c->ex.ev_main_end = t->ev[k + 1];
         } else {
             t = nullptr;
         }
     }
     ~TimeScope() {
-        if (t) (void)hipEventRecord(t->ev[k + 1], c->st);
+        if (!t) return;
+        if (!main) (void)hipEventRecord(t->ev[k + 1], c->st);
+        else if (c->ex.ev_main_end == t->ev[k + 1]) c->ex.mark_main_end();   // not consumed by a stencil launch
     }
+    bool main;
 };
 
 template <typename T> T *P(void *p) { return (T *)p; }
@@ -267,8 +274,17 @@ template <typename T> const T *CP(const void *p) { return (const T *)p; }
 int mg_mode(const jfnk_ctx *c) { return c->opt.fd_form == 1 ? M_FD_PLAIN : M_FD_DIFF; }
 int outer_mode(const jfnk_ctx *c) { return c->opt.fd_form == 2 ? M_FD_DIFF : M_FD_PLAIN; }
 
-double root_eps(jfnk_ctx *c, int prec) {
+// root of the FD step (Sec. 1: sqrt of the machine precision).  The
+// two-evaluation quotient loses about root^2 / root = root of its digits to
+// cancellation, so it needs the root of the precision it is evaluated in.
+// The difference form cancels nothing, so its step is taken with the FP64
+// root on every level: an FP32 level then evaluates the quotient for a step
+// small enough to stay in the linear regime of the residual, where a step
+// of sqrt(2^-23) (1 + ||x||) / ||v|| can move a localised direction far
+// into the nonlinear range of the coefficient.
+double root_eps(jfnk_ctx *c, int prec, int mode = M_FD_PLAIN) {
     if (c->opt.fd_root > 0.0) return c->opt.fd_root;
+    if (mode == M_FD_DIFF) return Prec<double>::root_eps;
     return prec == JFNK_F32 ? Prec<float>::root_eps : Prec<double>::root_eps;
 }
 
@@ -339,10 +355,7 @@ template <typename T> __global__ void k_copy_dirichlet(Grid g, int nc, const dou
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < g.nn;
          i += (long long)gridDim.x * blockDim.x) {
         int X, Y, Z;
-        long long q = i / g.NX;
-        X = (int)(i - q * g.NX);
-        Z = (int)(q / g.NY);
-        Y = (int)(q - (long long)Z * g.NY);
+        node_coords(g, i, X, Y, Z);
         if (is_dirichlet(g, X, Y, Z))
             for (int k = 0; k < nc; ++k) x[k * g.nn + i] = (T)u[k * g.nn + i];
     }
@@ -361,7 +374,8 @@ template <typename T> jfnk_status setup_levels(jfnk_ctx *c, const double *u, con
         // T* scratch for F: use t
         op_residual<T>(c->ex, L.g, c->ph, CP<T>(L.kap), CP<T>(L.x), nullptr, P<T>(L.t), P<T>(L.Ax), nullptr);
         c->ge[l] += 1;
-        vec_eps_num<T>(c->ex, L.g, nc, CP<T>(L.x), root_eps(c, c->vprec), c->opt.eps_mode, lslot(c, l, L_NUM));
+        vec_eps_num<T>(c->ex, L.g, nc, CP<T>(L.x), root_eps(c, c->vprec, mg_mode(c)), c->opt.eps_mode,
+                       lslot(c, l, L_NUM));
     }
     CHK(check_launch(c));
     for (int l = 1; l <= Lf; ++l) CHK(power_method<T>(c, l));
@@ -543,7 +557,7 @@ jfnk_status fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, doubl
             precondition<T>(c, V + (size_t)j * n, zj);
             CHK(apply_op<T>(c, op, zj, slot(c, S_ZN2), c->w));
             {
-                TimeScope ts(c, JFNK_TIMER_ARNOLDI);
+                TimeScope ts(c, JFNK_TIMER_ARNOLDI, false);
                 arn_dots(c->ex, n, V, n, j + 1, c->w, slot(c, S_H1));
                 arn_update(c->ex, n, V, n, j + 1, slot(c, S_H1), c->w, slot(c, S_H2), nullptr);
                 arn_update(c->ex, n, V, n, j + 1, slot(c, S_H2), c->w, nullptr, slot(c, S_W2));
@@ -679,7 +693,8 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
         CHK(do_setup(c, c->u, c->mf));
         const double eta = o.forcing == JFNK_FORCING_PAPER ? std::min(0.5, fn) : std::min(0.5, fn / f0);
         // outer FD step numerator from the FP64 iterate
-        vec_eps_num<double>(c->ex, c->lev[c->L].g, c->nc, c->u, root_eps(c, JFNK_F64), o.eps_mode, slot(c, S_NUM64));
+        vec_eps_num<double>(c->ex, c->lev[c->L].g, c->nc, c->u, root_eps(c, JFNK_F64, outer_mode(c)), o.eps_mode,
+                            slot(c, S_NUM64));
         int its = 0;
         double est = 0.0;
         jfnk_status ks = run_fgmres(c, OP_FD, c->F, -1.0, fn, eta * fn, c->dx, &its, &est);
@@ -839,11 +854,9 @@ jfnk_status jfnk_create(const jfnk_problem *p, const jfnk_options *o, void *ws, 
     plan(c, cv);
     c->ex.st = c->st;
     c->ex.red.part = c->part;
-    c->ex.red.count = c->cnt;
     c->ex.path = o->kernel_path;
     for (int l = 0; l < JFNK_MAX_LEVELS; ++l) c->ge[l] = 0.0;
     hipError_t e = hipMemsetAsync(c->scal, 0, NSLOT * sizeof(double), c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->cnt, 0, 256, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
         g_err = std::string("jfnk_create: ") + hipGetErrorString(e);
@@ -927,7 +940,8 @@ jfnk_status jfnk_jv(jfnk_ctx *c, int level, int prec, const void *u, const void 
             op_residual<double>(c->ex, g, c->ph, k, (const double *)u, nullptr, c->tmpA, nullptr, nullptr);
             A = c->tmpA;
         }
-        vec_eps_num<double>(c->ex, g, nc, (const double *)u, root_eps(c, JFNK_F64), c->opt.eps_mode, slot(c, S_DOT));
+        vec_eps_num<double>(c->ex, g, nc, (const double *)u, root_eps(c, JFNK_F64, outer_mode(c)), c->opt.eps_mode,
+                            slot(c, S_DOT));
         vec_dot<double, double>(c->ex, g.nn * nc, (const double *)v, (const double *)v, slot(c, S_XN2));
         op_jv<double, double>(c->ex, outer_mode(c), g, c->ph, k, (const double *)u, A, (const double *)v,
                               slot(c, S_DOT), slot(c, S_XN2), eps_override, (double *)Jv);
@@ -938,7 +952,8 @@ jfnk_status jfnk_jv(jfnk_ctx *c, int level, int prec, const void *u, const void 
             op_residual<float>(c->ex, g, c->ph, k, (const float *)u, nullptr, (float *)c->tmpA, nullptr, nullptr);
             A = (const float *)c->tmpA;
         }
-        vec_eps_num<float>(c->ex, g, nc, (const float *)u, root_eps(c, JFNK_F32), c->opt.eps_mode, slot(c, S_DOT));
+        vec_eps_num<float>(c->ex, g, nc, (const float *)u, root_eps(c, JFNK_F32, outer_mode(c)), c->opt.eps_mode,
+                           slot(c, S_DOT));
         vec_dot<float, float>(c->ex, g.nn * nc, (const float *)v, (const float *)v, slot(c, S_XN2));
         op_jv<float, float>(c->ex, outer_mode(c), g, c->ph, k, (const float *)u, A, (const float *)v,
                             slot(c, S_DOT), slot(c, S_XN2), eps_override, (float *)Jv);

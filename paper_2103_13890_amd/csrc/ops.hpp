@@ -12,6 +12,15 @@ struct Exec {
     hipStream_t st;
     Red red;
     int path;            // 0 auto, 1 node-centric, 2 z-marching tiles
+    // when set, recorded on st right after the next stencil kernel (before
+    // its reduction finish) and cleared: lets a timer bracket that kernel
+    mutable hipEvent_t ev_main_end = nullptr;
+    void mark_main_end() const {
+        if (ev_main_end) {
+            (void)hipEventRecord(ev_main_end, st);
+            ev_main_end = nullptr;
+        }
+    }
 };
 
 // a1 residual: F = A(u) - b (b nullable), A(u) -> Aout (nullable), ||F||^2 -> nrm2 (nullable)

@@ -21,11 +21,12 @@ __global__ __launch_bounds__(BLOCK) void k_energy(Grid g, Phys ph, const double 
     const long long ne = (long long)g.nx * g.ny * (DIM == 3 ? g.nz : 1);
     double sum[1] = {0.0};
     const long long stride = (long long)gridDim.x * blockDim.x;
+    const double rnx = 1.0 / g.nx, rny = 1.0 / g.ny;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += stride) {
-        const int ex = (int)(e % g.nx);
-        const long long q = e / g.nx;
-        const int ey = (int)(q % g.ny);
-        const int ez = (int)(q / g.ny);
+        unsigned q, r, q2, r2;
+        udivmod((unsigned)e, (unsigned)g.nx, rnx, q, r);
+        udivmod(q, (unsigned)g.ny, rny, q2, r2);
+        const int ex = (int)r, ey = (int)r2, ez = (int)q2;
         double w[NC][NV];
 #pragma unroll
         for (int a = 0; a < NV; ++a) {
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(BLOCK) void k_energy(Grid g, Phys ph, const double 
         if constexpr (KIND == JFNK_NEOHOOKE) sum[0] += elem_neohooke_energy<double>(w, ph, g.h);
         else sum[0] += elem_scalar_energy<DIM, KIND, double>(w[0], ph, g.h);
     }
-    grid_sum<1>(sum, red, FinStore<1>{out});
+    block_partials<1>(sum, red);
 }
 
 void op_energy(const Exec &ex, const Grid &g, const Phys &ph, const double *u, double *out) {
@@ -47,6 +48,7 @@ void op_energy(const Exec &ex, const Grid &g, const Phys &ph, const double *u, d
     else if (ph.kind == JFNK_PLAP && g.dim == 2) k_energy<2, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
     else if (ph.kind == JFNK_PLAP) k_energy<3, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
     else if (ph.kind == JFNK_NEOHOOKE) k_energy<3, JFNK_NEOHOOKE><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
+    finish<1>(ex.st, ex.red, nb, FinStore<1>{out});
 }
 
 // ---- exact VJP ---------------------------------------------------------------------

@@ -1,8 +1,8 @@
 // Deterministic reductions: 64-lane wavefront butterflies, a fixed-order
-// sum over the waves of a block, and a grid-level finish in which the last
-// block to arrive (integer ticket) sums the per-block partials in block
-// order.  No floating-point atomics, so every result is bitwise
-// reproducible for a given launch shape.
+// sum over the waves of a block, per-block partials, and a one-block
+// finishing kernel that sums the partials in block order.  No
+// floating-point atomics, so every result is bitwise reproducible for a
+// given launch shape.
 #pragma once
 #include "common.hpp"
 
@@ -13,8 +13,11 @@ constexpr int MAX_WAVES = 1024 / 64;
 
 struct Red {
     double *part;        // >= gridDim.x * NS partial sums
-    unsigned *count;     // arrival ticket, 0 between launches
 };
+
+// host side: launch the finishing kernel of a reduction over nb blocks
+template <int NS, class Fin>
+inline void finish(hipStream_t st, const Red &red, int nb, const Fin &fin);
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -41,40 +44,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NS], double *scratch, doub
     __syncthreads();
 }
 
-__device__ __forceinline__ double load_l2(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide sums of v.  The last block calls fin(tot) on thread 0 with the
-// totals, then resets the ticket.  Every block of the grid must call this.
-template <int NS, class Fin>
-__device__ __forceinline__ void grid_sum(double (&v)[NS], const Red &red, const Fin &fin) {
+// Per-block partial sums: the block's totals go to part[blockIdx.x * NS + k].
+// Every block of the grid must call this (it synchronises the block).
+template <int NS>
+__device__ __forceinline__ void block_partials(double (&v)[NS], const Red &red) {
     __shared__ double scratch[MAX_WAVES * NS];
     __shared__ double tot[NS];
-    __shared__ int last;
     block_sum<NS>(v, scratch, tot);
     if (threadIdx.x < NS) red.part[(size_t)blockIdx.x * NS + threadIdx.x] = tot[threadIdx.x];
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(red.count, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+// Second kernel of a grid reduction: one block sums the nb partials in
+// block order and hands the totals to fin on thread 0.  Launched on the same
+// stream right after the producing kernel, whose completion makes the
+// partials visible (no device-wide fence inside the producer, whose cost on
+// gfx950 is an L2 write-back per block).
+template <int NS, class Fin>
+__global__ __launch_bounds__(256) void k_finish(Red red, int nb, Fin fin) {
+    __shared__ double scratch[MAX_WAVES * NS];
+    __shared__ double tot[NS];
     double acc[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) {
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
 #pragma unroll
-        for (int k = 0; k < NS; ++k) acc[k] += load_l2(red.part + (size_t)b * NS + k);
+        for (int k = 0; k < NS; ++k) acc[k] += red.part[(size_t)b * NS + k];
     }
     block_sum<NS>(acc, scratch, tot);
-    if (threadIdx.x == 0) {
-        fin(tot);
-        *red.count = 0u;
-    }
+    if (threadIdx.x == 0) fin(tot);
 }
 
 // Finalisers: write the totals (or derived scalars) to device slots.
@@ -89,4 +86,11 @@ template <int NS> struct FinStore {
     }
 };
 
+}  // namespace jfnk
+
+namespace jfnk {
+template <int NS, class Fin>
+inline void finish(hipStream_t st, const Red &red, int nb, const Fin &fin) {
+    k_finish<NS, Fin><<<1, 256, 0, st>>>(red, nb, fin);
+}
 }  // namespace jfnk

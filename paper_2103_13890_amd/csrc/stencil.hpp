@@ -258,7 +258,7 @@ __global__ __launch_bounds__(BLOCK) void k_node(Grid g, Phys ph, const T *kap, c
         if (!dir) node_value<DIM, KIND, MODE, T, TV>(g, ph, kap, x, v, Ax, eps, X, Y, Z, i, val);
         epi.node(i, val, dir, sums);
     }
-    if constexpr (Epi::NS > 0) grid_sum<Epi::NS>(sums, red, epi);
+    if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
 }
 
 }  // namespace jfnk

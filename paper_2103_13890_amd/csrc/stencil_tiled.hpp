@@ -138,7 +138,7 @@ __global__ __launch_bounds__(TTX *TTY) void k_tiled(Grid g, Phys ph, const T *ka
             epi.node(i, val, dir, sums);
         }
     }
-    if constexpr (Epi::NS > 0) grid_sum<Epi::NS>(sums, red, epi);
+    if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
 }
 
 }  // namespace jfnk

@@ -46,12 +46,14 @@ __global__ void k_scale(Grid g, int nc, const TI *x, TO *y, double scale, const 
             s[0] += (double)v * (double)v;
         }
     }
-    if (out) grid_sum<1>(s, red, FinStore<1>{out});
+    if (out) block_partials<1>(s, red);
 }
 
 template <typename TI, typename TO>
 void vec_cast(const Exec &ex, const Grid &g, int nc, const TI *x, TO *y, double *nrm2) {
-    k_scale<TI, TO><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, x, y, 1.0, nullptr, ex.red, nrm2);
+    const int nb = vblocks(g.nn);
+    k_scale<TI, TO><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, y, 1.0, nullptr, ex.red, nrm2);
+    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void vec_cast<double, double>(const Exec &, const Grid &, int, const double *, double *, double *);
 template void vec_cast<double, float>(const Exec &, const Grid &, int, const double *, float *, double *);
@@ -61,7 +63,9 @@ template void vec_cast<float, float>(const Exec &, const Grid &, int, const floa
 template <typename T>
 void vec_scale(const Exec &ex, const Grid &g, int nc, const T *x, T *y, double scale, const double *rs,
                double *nrm2) {
-    k_scale<T, T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, x, y, scale, rs, ex.red, nrm2);
+    const int nb = vblocks(g.nn);
+    k_scale<T, T><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, y, scale, rs, ex.red, nrm2);
+    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void vec_scale<float>(const Exec &, const Grid &, int, const float *, float *, double, const double *, double *);
 template void vec_scale<double>(const Exec &, const Grid &, int, const double *, double *, double, const double *, double *);
@@ -76,7 +80,7 @@ struct FinEpsNum {
     }
 };
 template <typename T>
-__global__ void k_eps_num(Grid g, int nc, const T *x, Red red, FinEpsNum fin) {
+__global__ void k_eps_num(Grid g, int nc, const T *x, Red red) {
     double s[2] = {0.0, 0.0};
     GRID_STRIDE(i, g.nn) {
         if (dir_at(g, i)) continue;
@@ -86,7 +90,7 @@ __global__ void k_eps_num(Grid g, int nc, const T *x, Red red, FinEpsNum fin) {
             s[1] += fabs(v);
         }
     }
-    grid_sum<2>(s, red, fin);
+    block_partials<2>(s, red);
 }
 static double count_dofs(const Grid &g, int nc) {
     // DoFs = nodes off the Dirichlet faces
@@ -105,7 +109,9 @@ static double count_dofs(const Grid &g, int nc) {
 template <typename T>
 void vec_eps_num(const Exec &ex, const Grid &g, int nc, const T *x, double root, int mode, double *num) {
     double nd = count_dofs(g, nc);
-    k_eps_num<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, x, ex.red, FinEpsNum{num, root, nd > 0 ? nd : 1.0, mode});
+    const int nb = vblocks(g.nn);
+    k_eps_num<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, ex.red);
+    finish<2>(ex.st, ex.red, nb, FinEpsNum{num, root, nd > 0 ? nd : 1.0, mode});
 }
 template void vec_eps_num<float>(const Exec &, const Grid &, int, const float *, double, int, double *);
 template void vec_eps_num<double>(const Exec &, const Grid &, int, const double *, double, int, double *);
@@ -126,12 +132,14 @@ __global__ void k_cheb_zero(Grid g, int nc, const T *b, T *r, T *d, T *s, T inv_
             sm[0] += (double)dk * (double)dk;
         }
     }
-    grid_sum<1>(sm, red, FinStore<1>{out});
+    block_partials<1>(sm, red);
 }
 template <typename T>
 void vec_cheb_zero(const Exec &ex, const Grid &g, int nc, const T *b, T *r, T *d, T *s, double inv_theta,
                    double *d_nrm2) {
-    k_cheb_zero<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, b, r, d, s, (T)inv_theta, ex.red, d_nrm2);
+    const int nb = vblocks(g.nn);
+    k_cheb_zero<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, b, r, d, s, (T)inv_theta, ex.red, d_nrm2);
+    finish<1>(ex.st, ex.red, nb, FinStore<1>{d_nrm2});
 }
 template void vec_cheb_zero<float>(const Exec &, const Grid &, int, const float *, float *, float *, float *, double, double *);
 template void vec_cheb_zero<double>(const Exec &, const Grid &, int, const double *, double *, double *, double *, double, double *);
@@ -148,11 +156,13 @@ __global__ void k_add(Grid g, int nc, const T *s, const T *d, T *o, Red red, dou
             sm[0] += (double)v * (double)v;
         }
     }
-    if (out) grid_sum<1>(sm, red, FinStore<1>{out});
+    if (out) block_partials<1>(sm, red);
 }
 template <typename T>
 void vec_add(const Exec &ex, const Grid &g, int nc, const T *s, const T *d, T *o, double *nrm2) {
-    k_add<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, s, d, o, ex.red, nrm2);
+    const int nb = vblocks(g.nn);
+    k_add<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, s, d, o, ex.red, nrm2);
+    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void vec_add<float>(const Exec &, const Grid &, int, const float *, const float *, float *, double *);
 template void vec_add<double>(const Exec &, const Grid &, int, const double *, const double *, double *, double *);
@@ -179,12 +189,14 @@ __global__ void k_random(Grid g, int nc, unsigned long long s0, T *v, Red red, d
             sm[0] += (double)val * (double)val;
         }
     }
-    grid_sum<1>(sm, red, FinStore<1>{out});
+    block_partials<1>(sm, red);
 }
 template <typename T>
 void vec_random(const Exec &ex, const Grid &g, int nc, unsigned long long seed, int level, T *v, double *nrm2) {
     unsigned long long s0 = seed + ((unsigned long long)level << 32);
-    k_random<T><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, nc, s0, v, ex.red, nrm2);
+    const int nb = vblocks(g.nn);
+    k_random<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, s0, v, ex.red, nrm2);
+    finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void vec_random<float>(const Exec &, const Grid &, int, unsigned long long, int, float *, double *);
 template void vec_random<double>(const Exec &, const Grid &, int, unsigned long long, int, double *, double *);
@@ -202,11 +214,13 @@ template <typename TA, typename TB>
 __global__ void k_dot(long long n, const TA *x, const TB *y, Red red, double *out) {
     double sm[1] = {0.0};
     GRID_STRIDE(i, n) sm[0] += (double)x[i] * (double)y[i];
-    grid_sum<1>(sm, red, FinStore<1>{out});
+    block_partials<1>(sm, red);
 }
 template <typename TA, typename TB>
 void vec_dot(const Exec &ex, long long n, const TA *x, const TB *y, double *out) {
-    k_dot<TA, TB><<<vblocks(n), BLOCK, 0, ex.st>>>(n, x, y, ex.red, out);
+    const int nb = vblocks(n);
+    k_dot<TA, TB><<<nb, BLOCK, 0, ex.st>>>(n, x, y, ex.red, out);
+    finish<1>(ex.st, ex.red, nb, FinStore<1>{out});
 }
 template void vec_dot<double, double>(const Exec &, long long, const double *, const double *, double *);
 template void vec_dot<float, float>(const Exec &, long long, const float *, const float *, double *);
@@ -240,10 +254,12 @@ __global__ __launch_bounds__(BLOCK) void k_arn_dots(long long n, const double *V
         for (int j = 0; j < ARN_MAX; ++j)
             if (j < k) s[j] += V[j * ld + i] * wi;
     }
-    grid_sum<ARN_MAX>(s, red, FinStoreK{h, k});
+    block_partials<ARN_MAX>(s, red);
 }
 void arn_dots(const Exec &ex, long long n, const double *V, long long ld, int k, const double *w, double *h) {
-    k_arn_dots<<<vblocks(n, 1024), BLOCK, 0, ex.st>>>(n, V, ld, k, w, ex.red, h);
+    const int nb = vblocks(n, 1024);
+    k_arn_dots<<<nb, BLOCK, 0, ex.st>>>(n, V, ld, k, w, ex.red, h);
+    finish<ARN_MAX>(ex.st, ex.red, nb, FinStoreK{h, k});
 }
 
 // w -= sum_j V_j h_j; then h2 = V^T w (h2 != nullptr) or ||w||^2 -> nrm2
@@ -274,12 +290,14 @@ __global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double 
             s[0] += wi * wi;
         }
     }
-    if (h2) grid_sum<ARN_MAX>(s, red, FinStoreK{h2, k});
-    else grid_sum<ARN_MAX>(s, red, FinStoreK{nrm2, 1});
+    block_partials<ARN_MAX>(s, red);
 }
 void arn_update(const Exec &ex, long long n, const double *V, long long ld, int k, const double *h, double *w,
                 double *h2, double *nrm2) {
-    k_arn_update<<<vblocks(n, 1024), BLOCK, 0, ex.st>>>(n, V, ld, k, h, w, h2, nrm2, ex.red);
+    const int nb = vblocks(n, 1024);
+    k_arn_update<<<nb, BLOCK, 0, ex.st>>>(n, V, ld, k, h, w, h2, nrm2, ex.red);
+    if (h2) finish<ARN_MAX>(ex.st, ex.red, nb, FinStoreK{h2, k});
+    else finish<ARN_MAX>(ex.st, ex.red, nb, FinStoreK{nrm2, 1});
 }
 
 struct CombineArgs {
@@ -380,11 +398,13 @@ __global__ void k_restrict(Grid gf, Grid gc, int nc, const T *rf, T *rc, Red red
             sm[0] += (double)acc * (double)acc;
         }
     }
-    if (out) grid_sum<1>(sm, red, FinStore<1>{out});
+    if (out) block_partials<1>(sm, red);
 }
 template <typename T>
 void tr_restrict(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *rf, T *rc, double *nrm2) {
-    k_restrict<T><<<vblocks(gc.nn), BLOCK, 0, ex.st>>>(gf, gc, nc, rf, rc, ex.red, nrm2);
+    const int nb = vblocks(gc.nn);
+    k_restrict<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, rf, rc, ex.red, nrm2);
+    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void tr_restrict<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
 template void tr_restrict<double>(const Exec &, const Grid &, const Grid &, int, const double *, double *, double *);
@@ -421,11 +441,13 @@ __global__ void k_prolong_add(Grid gf, Grid gc, int nc, const T *cc, T *sf, Red 
             sm[0] += (double)s * (double)s;
         }
     }
-    if (out) grid_sum<1>(sm, red, FinStore<1>{out});
+    if (out) block_partials<1>(sm, red);
 }
 template <typename T>
 void tr_prolong_add(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *cc, T *sf, double *nrm2) {
-    k_prolong_add<T><<<vblocks(gf.nn), BLOCK, 0, ex.st>>>(gf, gc, nc, cc, sf, ex.red, nrm2);
+    const int nb = vblocks(gf.nn);
+    k_prolong_add<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, cc, sf, ex.red, nrm2);
+    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void tr_prolong_add<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
 template void tr_prolong_add<double>(const Exec &, const Grid &, const Grid &, int, const double *, double *, double *);
