@@ -52,17 +52,22 @@ __device__ __forceinline__ void stiff_apply(const T *u, T *Ku) {
     }
 }
 
-template <typename T> __device__ __forceinline__ T dsqrt(T x) { return sqrt(x); }
+// Square root and quotient: IEEE-rounded in FP64; in FP32 the hardware
+// approximations (about 1 ulp), which the FP32 multigrid levels tolerate.
+template <typename T> __device__ __forceinline__ T hw_sqrt(T x) { return sqrt(x); }
+template <> __device__ __forceinline__ float hw_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <typename T> __device__ __forceinline__ T hw_div(T a, T b) { return a / b; }
+template <> __device__ __forceinline__ float hw_div<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // (delta^2 + s)^e for the exponents the p-Laplacian needs
 template <typename T>
 __device__ __forceinline__ T plap_pow(T base, double p, int which) {
     // which 0: (p-2)/2, 1: p/2, 2: (p-4)/2
     if (p == 3.0) {
-        T r = sqrt(base);
-        return which == 0 ? r : (which == 1 ? base * r : T(1) / r);
+        T r = hw_sqrt(base);
+        return which == 0 ? r : (which == 1 ? base * r : hw_div(T(1), r));
     }
-    if (p == 2.0) return which == 0 ? T(1) : (which == 1 ? base : T(1) / base);
+    if (p == 2.0) return which == 0 ? T(1) : (which == 1 ? base : hw_div(T(1), base));
     double e = which == 0 ? 0.5 * (p - 2.0) : (which == 1 ? 0.5 * p : 0.5 * (p - 4.0));
     return (T)pow(base, (T)e);
 }
@@ -201,9 +206,9 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
         const T dsq = (T(2) * qxv + eps * qvv) * ih2;        // (s_w - s_x) / eps
         const T bw = bx + eps * dsq;
         if (ph.a0 == 3.0) {
-            const T kx = sqrt(bx);
-            kw = sqrt(bw);
-            dk = dsq / (kw + kx);
+            const T kx = hw_sqrt(bx);
+            kw = hw_sqrt(bw);
+            dk = hw_div(dsq, kw + kx);
         } else if (ph.a0 == 2.0) {
             kw = T(1);
             dk = T(0);

@@ -1,25 +1,38 @@
-// z-marching LDS-tiled evaluation for large 3D levels of the scalar kinds.
+// Row-marching LDS-tiled evaluation for 3D levels of the scalar kinds.
 //
-// A block owns a TTX x TTY column of nodes (one 64-wide wavefront per x row,
-// so every global access is a coalesced row) and TZC consecutive node
-// planes.  It marches up in z keeping two node planes of the state (and
-// direction, coefficient) in LDS with a one-node halo.  For each element
-// layer it evaluates every element of the tile (plus the one-element halo)
-// exactly once, writes the element's eight corner contributions to LDS, and
-// each node then sums the four contributions from below (carried in a
-// register from the previous layer) and the four from above.  The element
-// work, which dominates the arithmetic, is therefore done once per element
-// instead of once per adjacent node.
+// A block spans the whole x extent of the level: thread t owns the element
+// column ex = t (ceil(nx / 64) wavefronts, so every global access is a
+// coalesced row) and a tile of at most TROWS node rows in y and a chunk of
+// node planes in z.  The block marches up in z with the two node planes
+// that bound the current element layer in LDS (state x, direction v,
+// coefficient e^m), one halo row on each side in y.  For every element
+// layer each thread walks its column through the tile's element rows,
+// keeping the shared corner row in registers, so every element of the tile
+// is evaluated exactly once and the y and z neighbours of a node are summed
+// in registers.  The contributions that belong to the node column t + 1 are
+// handed over once per node through a small LDS row buffer.  Because a
+// block covers all of x, a level with 2^k + 1 nodes per row costs no
+// partial tile in x; in y and z the tiles are sized evenly.
 //
-// Workgroup ids are remapped so that the blocks dispatched to one XCD
-// (ids are dealt round-robin over the 8 XCDs) own a contiguous range of
-// tiles, keeping shared halo rows in that XCD's L2.
+// The next plane is fetched into registers before the element layer is
+// evaluated and written to LDS afterwards, so its global latency overlaps
+// the arithmetic.  Tiles are numbered y-fastest inside each z chunk and
+// workgroup ids are remapped so the blocks dispatched to one XCD (ids are
+// dealt round-robin over the 8 XCDs) own a contiguous range of tiles,
+// keeping the shared halo rows in that XCD's L2.
 #pragma once
 #include "stencil.hpp"
 
 namespace jfnk {
 
-constexpr int TTX = 64, TTY = 4, TZC = 16;
+constexpr int TROWS = 8;            // node rows per tile (register arrays)
+constexpr int TMAX_THREADS = 512;   // nx <= 512 elements per row
+
+struct TileArgs {
+    int nty, ntz;      // tiles along y and z
+    int pitch;         // LDS row pitch in entries (>= NX)
+    int srows;         // rows per LDS plane slot (node rows + 2)
+};
 
 __device__ __forceinline__ int xcd_tile(int id, int nb) {
     const int q = nb / 8, r = nb % 8;
@@ -27,29 +40,35 @@ __device__ __forceinline__ int xcd_tile(int id, int nb) {
     return xcd < r ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
 }
 
-inline int tiled_blocks(const Grid &g) {
-    return ((g.NX + TTX - 1) / TTX) * ((g.NY + TTY - 1) / TTY) * ((g.NZ + TZC - 1) / TZC);
+// Dynamic LDS of one block: two plane slots of x (T), e^m (T, INVCOEF) and
+// v (TV, FD modes), plus the TROWS x pitch hand-over buffer (T).
+template <typename T, typename TV, bool FD, bool INV>
+inline size_t tiled_lds_bytes(int pitch, int srows) {
+    const size_t plane = (size_t)srows * pitch;
+    return 2 * plane * sizeof(T) * (INV ? 2 : 1) + (size_t)TROWS * pitch * sizeof(T) +
+           (FD ? 2 * plane * sizeof(TV) : 0);
 }
 
 template <int KIND, int MODE, typename T, typename TV, class Epi>
-__global__ __launch_bounds__(TTX *TTY) void k_tiled(Grid g, Phys ph, const T *kap, const T *x, const TV *v,
-                                                    const T *Ax, FdStep fd, Epi epi, Red red) {
-    constexpr int HX = TTX + 2, HY = TTY + 2, EX = TTX + 1, EY = TTY + 1;
-    constexpr int NT = TTX * TTY;
+__global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T *kap, const T *x, const TV *v,
+                                                        const T *Ax, FdStep fd, Epi epi, Red red, TileArgs ta) {
     constexpr bool FD = MODE != M_RESID;
     constexpr bool INV = KIND == JFNK_INVCOEF;
-    __shared__ T sx[2][HY * HX];
-    __shared__ T sv[FD ? 2 : 1][FD ? HY * HX : 1];
-    __shared__ T sk[INV ? 2 : 1][INV ? HY * HX : 1];
-    __shared__ T se[8][EY * EX];
+    constexpr int R = TROWS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int P = ta.pitch;
+    const int plane = ta.srows * P;
+    T *sx = (T *)smem;                            // [2][plane]
+    T *sk = sx + 2 * plane;                       // [2][plane] (INVCOEF)
+    T *xb = sk + (INV ? 2 * plane : 0);           // [R][P] hand-over rows
+    TV *sv = (TV *)(xb + R * P);                  // [2][plane] (FD)
 
-    const int ntx = (g.NX + TTX - 1) / TTX, nty = (g.NY + TTY - 1) / TTY;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int tix = tile % ntx, rest = tile / ntx;
-    const int tiy = rest % nty, tiz = rest / nty;
-    const int x0 = tix * TTX, y0 = tiy * TTY, z0 = tiz * TZC;
-    const int z1 = min(z0 + TZC, g.NZ);
-    const int tx = threadIdx.x % TTX, ty = threadIdx.x / TTX;
+    const int tiy = tile % ta.nty, tiz = tile / ta.nty;
+    const int y0 = (int)((long long)tiy * g.NY / ta.nty), y1 = (int)((long long)(tiy + 1) * g.NY / ta.nty);
+    const int z0 = (int)((long long)tiz * g.NZ / ta.ntz), z1 = (int)((long long)(tiz + 1) * g.NZ / ta.ntz);
+    const int rows = y1 - y0;
+    const int t = threadIdx.x, nthr = blockDim.x;
     const double eps = fd.eps();
     const bool zero_fd = FD && eps == 0.0;
     const T e = (T)eps;
@@ -59,84 +78,173 @@ __global__ __launch_bounds__(TTX *TTY) void k_tiled(Grid g, Phys ph, const T *ka
 #pragma unroll
     for (int k = 0; k < (Epi::NS > 0 ? Epi::NS : 1); ++k) sums[k] = 0.0;
 
-    auto load_plane = [&](int pz) {
+    const bool own_col = t < g.NX;                 // loads and outputs node column t
+    const bool own_elem = t < g.nx;                // evaluates element column t
+    const bool extra = g.NX > nthr;                // column nx (= nthr) needs an extra loader
+    const bool xdir_t = ((g.dir & JFNK_FACE_XLO) && t == 0) || ((g.dir & JFNK_FACE_XHI) && t == g.nx);
+    const bool xdir_e = (g.dir & JFNK_FACE_XHI) != 0;   // column nx
+    auto ydir = [&](int gy) { return ((g.dir & JFNK_FACE_YLO) && gy == 0) || ((g.dir & JFNK_FACE_YHI) && gy == g.ny); };
+    auto zdir = [&](int gz) { return ((g.dir & JFNK_FACE_ZLO) && gz == 0) || ((g.dir & JFNK_FACE_ZHI) && gz == g.nz); };
+
+    // ---- plane fetch (global -> registers) and store (registers -> LDS) ----
+    T px[R + 2], pk[R + 2], qx = T(0), qk = T(0);
+    TV pv[R + 2], qv = TV(0);
+    auto fetch = [&](int pz) {
+        const bool zin = pz >= 0 && pz < g.NZ;
+        const bool zd = zdir(pz);
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) {
+            const int gy = y0 - 1 + r;
+            const bool in = zin && r < rows + 2 && gy >= 0 && gy < g.NY && own_col;
+            const int idx = (pz * g.NY + gy) * g.NX + t;
+            px[r] = in ? x[idx] : T(0);
+            if constexpr (FD) pv[r] = (in && !(xdir_t || zd || ydir(gy))) ? v[idx] : TV(0);
+            if constexpr (INV) pk[r] = in ? kap[idx] : T(0);
+        }
+        if (extra) {       // column nx, row t
+            const int gy = y0 - 1 + t;
+            const bool in = zin && t < rows + 2 && gy >= 0 && gy < g.NY;
+            const int idx = (pz * g.NY + gy) * g.NX + g.nx;
+            qx = in ? x[idx] : T(0);
+            if constexpr (FD) qv = (in && !(xdir_e || zd || ydir(gy))) ? v[idx] : TV(0);
+            if constexpr (INV) qk = in ? kap[idx] : T(0);
+        }
+    };
+    auto store = [&](int pz) {
         const int sl = pz & 1;
-        for (int k = threadIdx.x; k < HX * HY; k += NT) {
-            const int lx = k % HX, ly = k / HX;
-            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-            const bool in = gx >= 0 && gx < g.NX && gy >= 0 && gy < g.NY && pz >= 0 && pz < g.NZ;
-            const long long j = in ? node_index(g, gx, gy, pz) : 0;
-            sx[sl][k] = in ? x[j] : T(0);
-            if constexpr (FD) sv[sl][k] = (in && !is_dirichlet(g, gx, gy, pz)) ? (T)v[j] : T(0);
-            if constexpr (INV) sk[sl][k] = in ? kap[j] : T(0);
-        }
-    };
-    auto elem_layer = [&](int ez) {
-        const int p0 = ez & 1, p1 = (ez + 1) & 1;
-        for (int k = threadIdx.x; k < EX * EY; k += NT) {
-            const int lx = k % EX, ly = k / EX;
-            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-            const bool valid = !zero_fd && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && ez >= 0 && ez < g.nz;
-            T r[1][8];
-            if (valid) {
-                T xe[1][8], ve[1][8], kp[8];
+        if (own_col) {
 #pragma unroll
-                for (int a = 0; a < 8; ++a) {
-                    const int o = (ly + ((a >> 1) & 1)) * HX + lx + (a & 1);
-                    const int ps = (a >> 2) ? p1 : p0;
-                    xe[0][a] = sx[ps][o];
-                    ve[0][a] = FD ? sv[FD ? ps : 0][FD ? o : 0] : T(0);
-                    kp[a] = INV ? sk[INV ? ps : 0][INV ? o : 0] : T(0);
+            for (int r = 0; r < R + 2; ++r) {
+                if (r < rows + 2) {
+                    sx[sl * plane + r * P + t] = px[r];
+                    if constexpr (FD) sv[sl * plane + r * P + t] = pv[r];
+                    if constexpr (INV) sk[sl * plane + r * P + t] = pk[r];
                 }
-                elem_eval<3, KIND, MODE, T, 1, 8>(xe, ve, kp, e, ph, h, r);
-            } else {
-#pragma unroll
-                for (int a = 0; a < 8; ++a) r[0][a] = T(0);
             }
-#pragma unroll
-            for (int a = 0; a < 8; ++a) se[a][k] = r[0][a];
         }
-    };
-    // contributions of the element layer in se to the node (tx, ty) below
-    // (corners with a_z = 1 ... of the layer under the plane) and above
-    auto gather = [&](bool upper_corners) -> T {
-        T acc = T(0);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int c = upper_corners ? a + 4 : a;
-            const int idx = (ty + 1 - ((c >> 1) & 1)) * EX + (tx + 1 - (c & 1));
-            acc += se[c][idx];
+        if (extra && t < rows + 2) {
+            sx[sl * plane + t * P + g.nx] = qx;
+            if constexpr (FD) sv[sl * plane + t * P + g.nx] = qv;
+            if constexpr (INV) sk[sl * plane + t * P + g.nx] = qk;
         }
-        return acc;
     };
 
-    load_plane(z0 - 1);
-    load_plane(z0);
-    __syncthreads();
-    elem_layer(z0 - 1);
-    __syncthreads();
-    T carry = gather(true);        // element layer z0-1, corners on plane z0
-    for (int z = z0; z < z1; ++z) {
-        __syncthreads();
-        load_plane(z + 1);
-        __syncthreads();
-        elem_layer(z);
-        __syncthreads();
-        const T below = carry;
-        const T above = gather(false);   // element layer z, corners on plane z
-        carry = gather(true);            // element layer z, corners on plane z+1
-        const int gx = x0 + tx, gy = y0 + ty;
-        if (gx < g.NX && gy < g.NY) {
-            const long long i = node_index(g, gx, gy, z);
-            const bool dir = is_dirichlet(g, gx, gy, z);
-            T val[1] = {T(0)};
-            if (!dir && !zero_fd) {
-                T acc = below + above;
-                if constexpr (MODE == M_FD_PLAIN) acc = (acc - Ax[i]) * ie;
-                val[0] = acc;
+    // ---- element layer ez, walked row by row --------------------------------
+    // The node rows of the tile pass through two register FIFOs of depth R:
+    // C0/C1 hold the contributions of the layer below to node columns t and
+    // t + 1 (the carry), O the finished value of column t.  Every walk
+    // shifts both exactly R times, so after it C holds this layer's carry
+    // into the plane above and O[k] the value of node row k (the part for
+    // column t + 1 goes to the hand-over buffer).
+    T C0[R], C1[R], O[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) { C0[k] = T(0); C1[k] = T(0); O[k] = T(0); }
+    auto layer = [&](int ez) {
+        const bool lz = !zero_fd && ez >= 0 && ez < g.nz && own_elem;
+        const int lo = (ez & 1) * plane + t, hi = ((ez + 1) & 1) * plane + t;
+        // corners on the current row: [plane lo/hi][column t / t+1]
+        T cx[4], ck[4];
+        TV cv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { cx[c] = T(0); ck[c] = T(0); cv[c] = TV(0); }
+        auto row = [&](int r, T(&ox)[4], TV(&ov)[4], T(&ok)[4]) {
+            const int o = r * P;
+            ox[0] = sx[lo + o]; ox[1] = sx[lo + o + 1]; ox[2] = sx[hi + o]; ox[3] = sx[hi + o + 1];
+            if constexpr (FD) { ov[0] = sv[lo + o]; ov[1] = sv[lo + o + 1]; ov[2] = sv[hi + o]; ov[3] = sv[hi + o + 1]; }
+            if constexpr (INV) { ok[0] = sk[lo + o]; ok[1] = sk[lo + o + 1]; ok[2] = sk[hi + o]; ok[3] = sk[hi + o + 1]; }
+        };
+        if (lz) row(0, cx, cv, ck);
+        T pS0 = T(0), pS1 = T(0), pN0 = T(0), pN1 = T(0);
+#pragma unroll 1
+        for (int re = 0; re <= R; ++re) {
+            T r8[1][8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) r8[0][a] = T(0);
+            if (lz && re <= rows) {
+                T ux[4], uk[4];
+                TV uv[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { uk[c] = T(0); uv[c] = TV(0); }
+                row(re + 1, ux, uv, uk);
+                const int ey = y0 - 1 + re;
+                if (ey >= 0 && ey < g.ny) {
+                    // corner a = ax + 2 ay + 4 az
+                    const T xe[1][8] = {{cx[0], cx[1], ux[0], ux[1], cx[2], cx[3], ux[2], ux[3]}};
+                    T ve[1][8], kp[8];
+                    const TV vv[8] = {cv[0], cv[1], uv[0], uv[1], cv[2], cv[3], uv[2], uv[3]};
+                    const T kk[8] = {ck[0], ck[1], uk[0], uk[1], ck[2], ck[3], uk[2], uk[3]};
+#pragma unroll
+                    for (int a = 0; a < 8; ++a) { ve[0][a] = (T)vv[a]; kp[a] = kk[a]; }
+                    elem_eval<3, KIND, MODE, T, 1, 8>(xe, ve, kp, e, ph, h, r8);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { cx[c] = ux[c]; cv[c] = uv[c]; ck[c] = uk[c]; }
             }
-            epi.node(i, val, dir, sums);
+            if (re >= 1) {     // node row re - 1 is complete for this layer
+                const T t0 = C0[0] + (pS0 + r8[0][0]);
+                const T t1 = C1[0] + (pS1 + r8[0][1]);
+                const T n0 = pN0 + r8[0][4], n1 = pN1 + r8[0][5];
+                if (own_elem && re - 1 < rows) xb[(re - 1) * P + t + 1] = t1;
+#pragma unroll
+                for (int k = 0; k < R - 1; ++k) { C0[k] = C0[k + 1]; C1[k] = C1[k + 1]; O[k] = O[k + 1]; }
+                C0[R - 1] = n0; C1[R - 1] = n1; O[R - 1] = t0;
+            }
+            pS0 = r8[0][2]; pS1 = r8[0][3]; pN0 = r8[0][6]; pN1 = r8[0][7];
         }
+    };
+
+    if (t < R) xb[t * P] = T(0);        // node column 0 has no left element
+
+    // prologue: planes z0-1 and z0 in LDS, plane z0+1 in registers
+    fetch(z0 - 1);
+    store(z0 - 1);
+    fetch(z0);
+    store(z0);
+    fetch(z0 + 1);
+    __syncthreads();
+
+    // iteration z evaluates element layer z (planes z, z+1 in LDS) and, from
+    // z0 on, finishes node plane z; the first one only builds the carry.
+    for (int z = z0 - 1; z < z1; ++z) {
+        if (z >= z0 && z + 2 <= z1) fetch(z + 2);
+        layer(z);
+        __syncthreads();
+        if (z + 2 <= z1) store(z + 2);
+        if (z >= z0) {
+            const bool zd = zdir(z);
+#pragma unroll 1
+            for (int k = 0; k < rows; ++k) {
+                const int gy = y0 + k;
+                const bool yzd = zd || ydir(gy);
+                const int base = (z * g.NY + gy) * g.NX;
+                const T own = O[0];
+#pragma unroll
+                for (int j = 0; j < R - 1; ++j) O[j] = O[j + 1];
+                if (own_col) {
+                    const int i = base + t;
+                    const bool dir = yzd || xdir_t;
+                    T val[1] = {T(0)};
+                    if (!dir && !zero_fd) {
+                        T acc = own + xb[k * P + t];
+                        if constexpr (MODE == M_FD_PLAIN) acc = (acc - Ax[i]) * ie;
+                        val[0] = acc;
+                    }
+                    epi.node(i, val, dir, sums);
+                }
+                if (extra && t == nthr - 1) {     // node column nx: only element nx - 1 touches it
+                    const int i = base + g.nx;
+                    const bool dir = yzd || xdir_e;
+                    T val[1] = {T(0)};
+                    if (!dir && !zero_fd) {
+                        T acc = xb[k * P + g.nx];
+                        if constexpr (MODE == M_FD_PLAIN) acc = (acc - Ax[i]) * ie;
+                        val[0] = acc;
+                    }
+                    epi.node(i, val, dir, sums);
+                }
+            }
+        }
+        __syncthreads();
     }
     if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
 }

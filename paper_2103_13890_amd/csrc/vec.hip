@@ -1,6 +1,9 @@
 // Vector kernels: masked casts and scalings with fused norms, Chebyshev
 // start/finish, FD-step numerators, SplitMix64 start vectors, Gram-Schmidt
 // passes of flexible GMRES, and load-vector assembly.
+#include <array>
+#include <utility>
+
 #include "elem.hpp"
 #include "ops.hpp"
 
@@ -233,7 +236,92 @@ void vec_axpy(const Exec &ex, long long n, const double *x, double a, const doub
 }
 
 // ---- Gram-Schmidt passes ----------------------------------------------------------
+// The number of basis vectors K is a template parameter, so every load of a
+// pass is issued back to back (a run-time bound would put a branch, and a
+// wait, in front of each).  Up to 12 vectors a thread also takes two
+// elements per trip to keep more loads in flight.
 constexpr int ARN_MAX = 32;
+
+template <int K> struct ArnUnroll { static constexpr int U = K <= 12 ? 2 : 1; };
+
+// h = V^T w
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_arn_dots(long long n, const double *V, long long ld, const double *w,
+                                                    Red red) {
+    constexpr int U = ArnUnroll<K>::U;
+    double s[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) s[j] = 0.0;
+    const long long stride = (long long)gridDim.x * BLOCK;
+    long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        double wi[U], vj[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            wi[u] = w[i + u * stride];
+#pragma unroll
+            for (int j = 0; j < K; ++j) vj[u][j] = V[j * ld + i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < K; ++j) s[j] += vj[u][j] * wi[u];
+    }
+    if (U > 1 && i < n) {
+        const double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < K; ++j) s[j] += V[j * ld + i] * wi;
+    }
+    block_partials<K>(s, red);
+}
+
+// w -= V h; then h2 = V^T w (H2) or ||w||^2 (!H2) as partials
+template <int K, bool H2>
+__global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double *V, long long ld, const double *h,
+                                                      double *w, Red red) {
+    constexpr int U = ArnUnroll<K>::U;
+    constexpr int NS = H2 ? K : 1;
+    __shared__ double hs[K];
+    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double hj[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) hj[j] = hs[j];
+    double s[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) s[j] = 0.0;
+    auto finish_one = [&](long long idx, double a, const double *vj) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) a -= hj[j] * vj[j];
+        w[idx] = a;
+        if constexpr (H2) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) s[j] += vj[j] * a;
+        } else {
+            s[0] += a * a;
+        }
+    };
+    const long long stride = (long long)gridDim.x * BLOCK;
+    long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        double wi[U], vj[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            wi[u] = w[i + u * stride];
+#pragma unroll
+            for (int j = 0; j < K; ++j) vj[u][j] = V[j * ld + i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) finish_one(i + u * stride, wi[u], vj[u]);
+    }
+    if (U > 1 && i < n) {
+        double vj[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
+        finish_one(i, w[i], vj);
+    }
+    block_partials<NS>(s, red);
+}
 
 struct FinStoreK {
     double *out;
@@ -243,80 +331,84 @@ struct FinStoreK {
     }
 };
 
-__global__ __launch_bounds__(BLOCK) void k_arn_dots(long long n, const double *V, long long ld, int k,
-                                                    const double *w, Red red, double *h) {
-    double s[ARN_MAX];
-#pragma unroll
-    for (int j = 0; j < ARN_MAX; ++j) s[j] = 0.0;
-    GRID_STRIDE(i, n) {
-        const double wi = w[i];
-#pragma unroll
-        for (int j = 0; j < ARN_MAX; ++j)
-            if (j < k) s[j] += V[j * ld + i] * wi;
-    }
-    block_partials<ARN_MAX>(s, red);
+static inline int arn_blocks(long long n) { return vblocks(n, 2048); }
+
+template <int K> void arn_dots_k(const Exec &ex, long long n, const double *V, long long ld, const double *w,
+                                 double *h) {
+    const int nb = arn_blocks(n);
+    k_arn_dots<K><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, w, ex.red);
+    finish<K>(ex.st, ex.red, nb, FinStoreK{h, K});
 }
-void arn_dots(const Exec &ex, long long n, const double *V, long long ld, int k, const double *w, double *h) {
-    const int nb = vblocks(n, 1024);
-    k_arn_dots<<<nb, BLOCK, 0, ex.st>>>(n, V, ld, k, w, ex.red, h);
-    finish<ARN_MAX>(ex.st, ex.red, nb, FinStoreK{h, k});
+template <int K> void arn_update_k(const Exec &ex, long long n, const double *V, long long ld, const double *h,
+                                   double *w, double *h2, double *nrm2) {
+    const int nb = arn_blocks(n);
+    if (h2) {
+        k_arn_update<K, true><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, w, ex.red);
+        finish<K>(ex.st, ex.red, nb, FinStoreK{h2, K});
+    } else {
+        k_arn_update<K, false><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, w, ex.red);
+        finish<1>(ex.st, ex.red, nb, FinStoreK{nrm2, 1});
+    }
 }
 
-// w -= sum_j V_j h_j; then h2 = V^T w (h2 != nullptr) or ||w||^2 -> nrm2
-__global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double *V, long long ld, int k,
-                                                      const double *h, double *w, double *h2, double *nrm2,
-                                                      Red red) {
-    __shared__ double hs[ARN_MAX];
-    if (threadIdx.x < ARN_MAX) hs[threadIdx.x] = threadIdx.x < (unsigned)k ? h[threadIdx.x] : 0.0;
-    __syncthreads();
-    double s[ARN_MAX];
-#pragma unroll
-    for (int j = 0; j < ARN_MAX; ++j) s[j] = 0.0;
-    GRID_STRIDE(i, n) {
-        double wi = w[i];
-        double vj[ARN_MAX];
-#pragma unroll
-        for (int j = 0; j < ARN_MAX; ++j)
-            if (j < k) {
-                vj[j] = V[j * ld + i];
-                wi -= hs[j] * vj[j];
-            }
-        w[i] = wi;
-        if (h2) {
-#pragma unroll
-            for (int j = 0; j < ARN_MAX; ++j)
-                if (j < k) s[j] += vj[j] * wi;
-        } else {
-            s[0] += wi * wi;
-        }
-    }
-    block_partials<ARN_MAX>(s, red);
+using DotsFn = void (*)(const Exec &, long long, const double *, long long, const double *, double *);
+using UpdFn = void (*)(const Exec &, long long, const double *, long long, const double *, double *, double *,
+                       double *);
+template <int... Ks> constexpr std::array<DotsFn, sizeof...(Ks)> dots_table(std::integer_sequence<int, Ks...>) {
+    return {&arn_dots_k<Ks + 1>...};
+}
+template <int... Ks> constexpr std::array<UpdFn, sizeof...(Ks)> upd_table(std::integer_sequence<int, Ks...>) {
+    return {&arn_update_k<Ks + 1>...};
+}
+static constexpr auto kDots = dots_table(std::make_integer_sequence<int, ARN_MAX>{});
+static constexpr auto kUpd = upd_table(std::make_integer_sequence<int, ARN_MAX>{});
+
+void arn_dots(const Exec &ex, long long n, const double *V, long long ld, int k, const double *w, double *h) {
+    if (k < 1 || k > ARN_MAX) return;
+    kDots[k - 1](ex, n, V, ld, w, h);
 }
 void arn_update(const Exec &ex, long long n, const double *V, long long ld, int k, const double *h, double *w,
                 double *h2, double *nrm2) {
-    const int nb = vblocks(n, 1024);
-    k_arn_update<<<nb, BLOCK, 0, ex.st>>>(n, V, ld, k, h, w, h2, nrm2, ex.red);
-    if (h2) finish<ARN_MAX>(ex.st, ex.red, nb, FinStoreK{h2, k});
-    else finish<ARN_MAX>(ex.st, ex.red, nb, FinStoreK{nrm2, 1});
+    if (k < 1 || k > ARN_MAX) return;
+    kUpd[k - 1](ex, n, V, ld, h, w, h2, nrm2);
 }
 
+// x += Z y  (y passed by value)
 struct CombineArgs {
     double y[ARN_MAX];
 };
-template <typename TZ>
-__global__ __launch_bounds__(BLOCK) void k_arn_combine(long long n, const TZ *Z, long long ld, int k,
-                                                       CombineArgs ya, double *x) {
+template <typename TZ, int K>
+__global__ __launch_bounds__(BLOCK) void k_arn_combine(long long n, const TZ *Z, long long ld, CombineArgs ya,
+                                                       double *x) {
     GRID_STRIDE(i, n) {
+        TZ zj[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) zj[j] = Z[j * ld + i];
         double acc = x[i];
-        for (int j = 0; j < k; ++j) acc += ya.y[j] * (double)Z[j * ld + i];
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc += ya.y[j] * (double)zj[j];
         x[i] = acc;
     }
 }
+template <typename TZ, int K>
+void arn_combine_k(const Exec &ex, long long n, const TZ *Z, long long ld, const CombineArgs &a, double *x) {
+    k_arn_combine<TZ, K><<<vblocks(n), BLOCK, 0, ex.st>>>(n, Z, ld, a, x);
+}
+template <typename TZ> using CombFn = void (*)(const Exec &, long long, const TZ *, long long, const CombineArgs &,
+                                               double *);
+template <typename TZ, int... Ks>
+constexpr std::array<CombFn<TZ>, sizeof...(Ks)> comb_table(std::integer_sequence<int, Ks...>) {
+    return {&arn_combine_k<TZ, Ks + 1>...};
+}
+
+// y: host array of k coefficients
 template <typename TZ>
 void arn_combine(const Exec &ex, long long n, const TZ *Z, long long ld, int k, const double *y, double *x) {
+    static constexpr auto tab = comb_table<TZ>(std::make_integer_sequence<int, ARN_MAX>{});
+    if (k < 1 || k > ARN_MAX) return;
     CombineArgs a;
     for (int j = 0; j < ARN_MAX; ++j) a.y[j] = j < k ? y[j] : 0.0;
-    k_arn_combine<TZ><<<vblocks(n), BLOCK, 0, ex.st>>>(n, Z, ld, k, a, x);
+    tab[k - 1](ex, n, Z, ld, a, x);
 }
 template void arn_combine<float>(const Exec &, long long, const float *, long long, int, const double *, double *);
 template void arn_combine<double>(const Exec &, long long, const double *, long long, int, const double *, double *);

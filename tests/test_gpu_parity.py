@@ -114,6 +114,45 @@ def test_jv_f64(kind, path, form):
     assert rel(to_np(Jv), OD.jvp(pb, g, u, v, m)) < 1e-5
 
 
+# Row-tiled kernel shapes: x extents that are a multiple of 64 (the last node
+# column has its own loader), two wavefronts with a partial second one,
+# natural faces on the high sides, several y tiles and z chunks.
+TILE_CASES = [
+    ('plap', (64, 17, 9), W.ALL3),
+    ('plap', (64, 17, 9), [(0, 0), (1, 0), (2, 0)]),
+    ('invcoef', (100, 19, 7), [(0, 1), (1, 1), (2, 0)]),
+    ('bratu', (33, 9, 13), W.ALL3),
+]
+
+
+def _tile_workload(kind, n, faces):
+    base = {'plap': 'plap3d-128', 'invcoef': 'invcoef3d-128', 'bratu': 'plap3d-128'}[kind]
+    w = W.scaled(base, n, nlevels=1, vcycle_prec=0)
+    w['faces'] = faces
+    if kind == 'bratu':
+        w.update(kind='bratu', params=(2.0,))
+    return w
+
+
+@pytest.mark.parametrize('case', range(len(TILE_CASES)))
+def test_tiled_shapes(case):
+    kind, n, faces = TILE_CASES[case]
+    w = _tile_workload(kind, n, faces)
+    pb, g = oracle_problem(w), oracle_grid(w)
+    u, v, m, b = _inputs(w, 120 + case, True)
+    md = to_dev(m) if m is not None else None
+    Au = OP.apply_A(pb, g, u, m)
+    eps_t = 1e-2 * (1 + np.linalg.norm(u)) / np.linalg.norm(v)
+    for path in (1, 2):
+        ctx = make_ctx(w, kernel_path=path, fd_form=2)
+        F = api.jfnk_residual(ctx, 0, to_dev(u), md, to_dev(b))
+        assert rel(to_np(F), OP.residual(pb, g, u, b, m)) < 1e-12, path
+        Jv = api.jfnk_jv(ctx, 0, to_dev(u), to_dev(v), md, eps_override=eps_t)
+        assert rel(to_np(Jv), OM.fd_jv(pb, g, u, Au, v, m, eps_t)) < 1e-12, path
+        Jv32 = api.jfnk_jv(ctx, 0, to_dev(u, torch.float32), to_dev(v, torch.float32), md, eps_override=eps_t)
+        assert rel(to_np(Jv32), OM.fd_jv(pb, g, u, Au, v, m, eps_t)) < 1e-4, path
+
+
 @pytest.mark.parametrize('kind', KINDS)
 @pytest.mark.parametrize('path', [1, 2])
 def test_jv_f32_difference_form(kind, path):
