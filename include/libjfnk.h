@@ -258,6 +258,18 @@ jfnk_status mg_vcycle(jfnk_ctx *ctx, const double *b_fine, double *s_fine);
 jfnk_status jfnk_solve(jfnk_ctx *ctx, double *u, const double *coef, const double *b,
                        jfnk_report *rep);
 
+/* Load stepping (Sec. 3, the hyperelastic example applies its boundary data
+ * in increments): solves with the loads (k / nsteps) b for k = 1..nsteps,
+ * each increment a jfnk_solve from the previous increment's solution.  A
+ * failed increment is retried with half the step (down to 1e-6 of the load).
+ * u: FP64, in the initial iterate, out the solution of the last accepted
+ * increment.  rep (host, nullable) sums the iteration counts and GE over all
+ * increments; its histories hold one entry per attempted increment: fnorm,
+ * alpha = load fraction reached, eta = increment size, lin = Krylov
+ * iterations.  JFNK_OK when the full load was reached. */
+jfnk_status jfnk_solve_steps(jfnk_ctx *ctx, double *u, const double *coef, const double *b,
+                             int nsteps, jfnk_report *rep);
+
 /* ---- a13, a14: exact vector-Jacobian products --------------------------- */
 /* wrt 0: out = J_l(u)^T lam on the DoFs (exact element Jacobians; equal to
  *        J lam for the variational kinds).

@@ -68,7 +68,7 @@ EXPORTS = [
     'jfnk_default_options', 'jfnk_workspace_bytes', 'jfnk_create', 'jfnk_destroy', 'jfnk_last_error',
     'jfnk_version', 'jfnk_abi_sizes', 'jfnk_level_info', 'jfnk_residual', 'jfnk_energy', 'jfnk_jv',
     'mg_project', 'mg_restrict', 'mg_prolong_add', 'mg_setup', 'mg_reset_eigvecs', 'mg_get_level',
-    'mg_get_lambda', 'mg_smooth', 'mg_coarse_solve', 'mg_vcycle', 'jfnk_solve', 'jfnk_vjp',
+    'mg_get_lambda', 'mg_smooth', 'mg_coarse_solve', 'mg_vcycle', 'jfnk_solve', 'jfnk_solve_steps', 'jfnk_vjp',
     'jfnk_adjoint_solve', 'jfnk_assemble_load', 'jfnk_timer_enable', 'jfnk_timer_read',
 ]
 
@@ -110,6 +110,7 @@ def load():
                                     ctypes.POINTER(c_int)]),
         'mg_vcycle': (c_int, [vp, vp, vp]),
         'jfnk_solve': (c_int, [vp, vp, vp, vp, R]),
+        'jfnk_solve_steps': (c_int, [vp, vp, vp, vp, c_int, R]),
         'jfnk_vjp': (c_int, [vp, c_int, c_int, vp, vp, vp, vp]),
         'jfnk_adjoint_solve': (c_int, [vp, vp, vp, vp, c_dbl, vp, R]),
         'jfnk_assemble_load': (c_int, [vp, c_int, ctypes.POINTER(c_dbl), c_int, vp]),

@@ -264,6 +264,23 @@ def jfnk_solve(ctx, u, coef=None, b=None, raise_on_fail=False):
     return d
 
 
+def jfnk_solve_steps(ctx, u, nsteps, coef=None, b=None, raise_on_fail=False):
+    """Load stepping: solve with loads (k / nsteps) b, k = 1..nsteps, in place;
+    returns the summed report dict (see jfnk_solve_steps in libjfnk.h)."""
+    L = ctx.nlevels - 1
+    rep = _lib.Report()
+    st = ctx.lib.jfnk_solve_steps(ctx.h, _ptr(u, ctx, L, torch.float64, name='u'),
+                                  _ptr(coef, ctx, L, torch.float64, False, 'coef'),
+                                  _ptr(b, ctx, L, torch.float64, name='b'), int(nsteps), ctypes.byref(rep))
+    d = rep.to_dict(ctx.nlevels)
+    if st != _lib.OK:
+        msg = ctx.lib.jfnk_last_error(ctx.h)
+        d['error'] = msg.decode() if msg else ''
+        if raise_on_fail or st in (_lib.E_INVAL, _lib.E_DEVICE):
+            raise JfnkError(st, d['error'])
+    return d
+
+
 # ---- a13, a14, a15 ------------------------------------------------------------------------
 def jfnk_vjp(ctx, level, wrt, u, lam, coef=None, out=None):
     out = ctx.empty(level, torch.float64, comps=(wrt == 0)) if out is None else out
@@ -308,3 +325,37 @@ def jfnk_timer_read(ctx, which):
     ms = ctypes.c_double()
     ctx.check(ctx.lib.jfnk_timer_read(ctx.h, int(which), ctypes.byref(cnt), ctypes.byref(ms)))
     return cnt.value, ms.value
+
+
+# ---- a15: differentiable solve ----------------------------------------------------------------
+class JFNKSolve(torch.autograd.Function):
+    """u = JFNKSolve.apply(coef, b, ctx, u0, adjoint_rtol): the root of
+    F(u; coef) = A(u; coef) - b on the finest level (jfnk_solve from u0, or
+    from 0).  Backward (implicit-function theorem): with J(u)^T lam = dL/du
+    (jfnk_adjoint_solve, the multigrid of the converged u as preconditioner),
+    dL/dcoef = -(dF/dcoef)^T lam (jfnk_vjp, wrt 1) and dL/db = lam.  coef is
+    the INVCOEF field m (None for the other kinds)."""
+
+    @staticmethod
+    def forward(fctx, coef, b, ctx, u0=None, adjoint_rtol=1e-10):
+        L = ctx.nlevels - 1
+        u = ctx.empty(L, torch.float64).zero_() if u0 is None else u0.detach().clone()
+        jfnk_solve(ctx, u, None if coef is None else coef.detach(), None if b is None else b.detach(),
+                   raise_on_fail=True)
+        fctx.jctx = ctx
+        fctx.rtol = adjoint_rtol
+        fctx.has_coef = coef is not None
+        fctx.save_for_backward(u, coef.detach() if coef is not None else None)
+        return u
+
+    @staticmethod
+    def backward(fctx, gu):
+        ctx = fctx.jctx
+        u, coef = fctx.saved_tensors
+        L = ctx.nlevels - 1
+        lam, _ = jfnk_adjoint_solve(ctx, u, gu.contiguous().to(torch.float64), coef=coef, rtol=fctx.rtol)
+        g_coef = None
+        if fctx.has_coef and fctx.needs_input_grad[0]:
+            g_coef = -jfnk_vjp(ctx, L, 1, u, lam, coef=coef)
+        g_b = lam if fctx.needs_input_grad[1] else None
+        return g_coef, g_b, None, None, None

@@ -1087,12 +1087,10 @@ jfnk_status mg_vcycle(jfnk_ctx *c, const double *b, double *s) {
     return check_launch(c);
 }
 
-jfnk_status jfnk_solve(jfnk_ctx *c, double *u, const double *coef, const double *b, jfnk_report *rep) {
-    if (!c) return fail(nullptr, JFNK_E_INVAL, "null context");
-    if (!u) return fail(c, JFNK_E_INVAL, "null u");
-    if (c->prob.kind == JFNK_INVCOEF && !coef) return fail(c, JFNK_E_INVAL, "INVCOEF needs coef");
-    jfnk_report local;
-    if (!rep) rep = &local;
+// One Newton solve with load scale * b from u; u receives the last
+// accepted iterate when write_back or on success.
+static jfnk_status solve_once(jfnk_ctx *c, double *u, const double *coef, const double *b, double scale,
+                              jfnk_report *rep, bool write_back) {
     report_init(c, rep);
     HIPCHK(c, hipMemsetAsync(c->scal + S_COARSE, 0, 8 * sizeof(double), c->st));
     if (!c->t0) {
@@ -1102,7 +1100,7 @@ jfnk_status jfnk_solve(jfnk_ctx *c, double *u, const double *coef, const double 
     HIPCHK(c, hipEventRecord(c->t0, c->st));
     const Grid &g = c->lev[c->L].g;
     HIPCHK(c, hipMemcpyAsync(c->u, u, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-    if (b) vec_cast<double, double>(c->ex, g, c->nc, b, c->bm, nullptr);
+    if (b) vec_scale<double>(c->ex, g, c->nc, b, c->bm, scale, nullptr, nullptr);
     else vec_fill<double>(c->ex, c->bm, c->n, 0.0);
     if (c->prob.kind == JFNK_INVCOEF) {
         HIPCHK(c, hipMemcpyAsync(c->mf, coef, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->st));
@@ -1110,7 +1108,8 @@ jfnk_status jfnk_solve(jfnk_ctx *c, double *u, const double *coef, const double 
     }
     c->have_eigs = false;
     jfnk_status s = newton(c, rep);
-    HIPCHK(c, hipMemcpyAsync(u, c->u, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    if (s == JFNK_OK || write_back)
+        HIPCHK(c, hipMemcpyAsync(u, c->u, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
     HIPCHK(c, hipEventRecord(c->t1, c->st));
     HIPCHK(c, hipEventSynchronize(c->t1));
     float ms = 0.f;
@@ -1119,6 +1118,65 @@ jfnk_status jfnk_solve(jfnk_ctx *c, double *u, const double *coef, const double 
     report_finish(c, rep);
     rep->status = s;
     return s;
+}
+
+jfnk_status jfnk_solve(jfnk_ctx *c, double *u, const double *coef, const double *b, jfnk_report *rep) {
+    if (!c) return fail(nullptr, JFNK_E_INVAL, "null context");
+    if (!u) return fail(c, JFNK_E_INVAL, "null u");
+    if (c->prob.kind == JFNK_INVCOEF && !coef) return fail(c, JFNK_E_INVAL, "INVCOEF needs coef");
+    jfnk_report local;
+    if (!rep) rep = &local;
+    return solve_once(c, u, coef, b, 1.0, rep, true);
+}
+
+jfnk_status jfnk_solve_steps(jfnk_ctx *c, double *u, const double *coef, const double *b, int nsteps,
+                             jfnk_report *rep) {
+    if (!c) return fail(nullptr, JFNK_E_INVAL, "null context");
+    if (!u) return fail(c, JFNK_E_INVAL, "null u");
+    if (nsteps < 1) return fail(c, JFNK_E_INVAL, "nsteps must be >= 1");
+    if (c->prob.kind == JFNK_INVCOEF && !coef) return fail(c, JFNK_E_INVAL, "INVCOEF needs coef");
+    jfnk_report local, one;
+    if (!rep) rep = &local;
+    std::memset(rep, 0, sizeof(*rep));
+    double t = 0.0, dt = 1.0 / nsteps;
+    bool first = true;
+    jfnk_status last = JFNK_OK;
+    while (t < 1.0 - 1e-12) {
+        const double step = std::min(dt, 1.0 - t);
+        last = solve_once(c, u, coef, b, t + step, &one, false);
+        if (last == JFNK_E_DEVICE || last == JFNK_E_INVAL) return last;
+        if (first) rep->fnorm0 = one.fnorm0;
+        first = false;
+        rep->newton_iters += one.newton_iters;
+        rep->linear_iters += one.linear_iters;
+        rep->coarse_calls += one.coarse_calls;
+        rep->coarse_iters += one.coarse_iters;
+        rep->neg_curv += one.neg_curv;
+        rep->ge_effective += one.ge_effective;
+        for (int l = 0; l < JFNK_MAX_LEVELS; ++l) {
+            rep->ge_level[l] += one.ge_level[l];
+            rep->lambda[l] = one.lambda[l];
+        }
+        rep->last_shift = one.last_shift;
+        rep->time_ms += one.time_ms;
+        rep->fnorm = one.fnorm;
+        if (rep->nhist < JFNK_MAX_HIST) {          // one history entry per attempted increment
+            rep->fnorm_hist[rep->nhist] = one.fnorm;
+            rep->alpha_hist[rep->nhist] = t + step;
+            rep->eta_hist[rep->nhist] = step;
+            rep->lin_hist[rep->nhist] = one.linear_iters;
+            rep->nhist++;
+        }
+        if (last == JFNK_OK) {
+            t += step;
+        } else {
+            dt = 0.5 * step;
+            if (dt < 1e-6) break;
+        }
+    }
+    const jfnk_status res = t >= 1.0 - 1e-12 ? JFNK_OK : (last == JFNK_OK ? JFNK_E_NOCONV : last);
+    rep->status = res;
+    return res;
 }
 
 jfnk_status jfnk_vjp(jfnk_ctx *c, int level, int wrt, const double *u, const double *coef, const double *lam,

@@ -37,22 +37,29 @@ struct FdStep {
 };
 
 // ---- epilogues ---------------------------------------------------------------
-// NS: number of grid sums; NCOMP: components; node(i, val, dir, sums);
-// operator()(totals) runs once in the last block.
+// NS: number of grid sums; NCOMP: components; NIN: values read per node and
+// component.  load(i, in) reads them (issued ahead of the element work by
+// the tiled kernel), node(i, val, dir, sums, in) consumes val at node i;
+// operator()(totals) runs in the reduction's finishing kernel.
 
 // F = val - b (b nullable); Aout (nullable) receives val; ||F||^2 -> out
 template <typename T, int NC> struct EpiResidual {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
+    static constexpr int NIN = 1;
     const T *b;
     T *F;
     T *Aout;
     long long nn;
     double *out;
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *s) const {
+    __device__ __forceinline__ void load(long long i, T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) in[c] = b ? b[c * nn + i] : T(0);
+    }
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *s, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            T f = dir ? T(0) : (b ? val[c] - b[c * nn + i] : val[c]);
+            T f = dir ? T(0) : val[c] - in[c];
             F[c * nn + i] = f;
             if (Aout) Aout[c * nn + i] = dir ? T(0) : val[c];
             s[0] += (double)f * (double)f;
@@ -65,9 +72,11 @@ template <typename T, int NC> struct EpiResidual {
 template <typename T, int NC> struct EpiJv {
     static constexpr int NS = 0;
     static constexpr int NCOMP = NC;
+    static constexpr int NIN = 0;
     T *Jv;
     long long nn;
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *) const {
+    __device__ __forceinline__ void load(long long, T *) const {}
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *, const T *) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) Jv[c * nn + i] = dir ? T(0) : val[c];
     }
@@ -79,12 +88,22 @@ template <typename T, int NC> struct EpiJv {
 template <typename T, int NC> struct EpiCheb {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
+    static constexpr int NIN = 3;
     const T *d;
     T *r, *s, *dn;
     T c1, c2;
     long long nn;
     double *out;
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm) const {
+    __device__ __forceinline__ void load(long long i, T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            in[3 * c] = d[k];
+            in[3 * c + 1] = r[k];
+            in[3 * c + 2] = s[k];
+        }
+    }
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const long long k = c * nn + i;
@@ -92,9 +111,9 @@ template <typename T, int NC> struct EpiCheb {
                 r[k] = T(0); s[k] = T(0); dn[k] = T(0);
                 continue;
             }
-            const T dk = d[k];
-            s[k] = s[k] + dk;
-            const T rk = r[k] - val[c];
+            const T dk = in[3 * c];
+            s[k] = in[3 * c + 2] + dk;
+            const T rk = in[3 * c + 1] - val[c];
             r[k] = rk;
             const T dnew = c1 * dk + c2 * rk;
             dn[k] = dnew;
@@ -108,15 +127,17 @@ template <typename T, int NC> struct EpiCheb {
 template <typename T, int NC> struct EpiResidJv {
     static constexpr int NS = 0;
     static constexpr int NCOMP = NC;
+    static constexpr int NIN = 1;
     const T *b;
     T *t;
     long long nn;
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *) const {
+    __device__ __forceinline__ void load(long long i, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
-            t[k] = dir ? T(0) : b[k] - val[c];
-        }
+        for (int c = 0; c < NC; ++c) in[c] = b[c * nn + i];
+    }
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *, const T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) t[c * nn + i] = dir ? T(0) : in[c] - val[c];
     }
     __device__ void operator()(const double *) const {}
 };
@@ -125,17 +146,22 @@ template <typename T, int NC> struct EpiResidJv {
 template <typename T, int NC> struct EpiChebInit {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
+    static constexpr int NIN = 1;
     const T *b;
     T *r, *d;
     T inv_theta;
     long long nn;
     double *out;
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm) const {
+    __device__ __forceinline__ void load(long long i, T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) in[c] = b[c * nn + i];
+    }
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const long long k = c * nn + i;
             if (dir) { r[k] = T(0); d[k] = T(0); continue; }
-            const T rk = b[k] - val[c];
+            const T rk = in[c] - val[c];
             r[k] = rk;
             const T dk = rk * inv_theta;
             d[k] = dk;
@@ -149,17 +175,22 @@ template <typename T, int NC> struct EpiChebInit {
 template <typename T, int NC> struct EpiPower {
     static constexpr int NS = 2;
     static constexpr int NCOMP = NC;
+    static constexpr int NIN = 1;
     const T *v;
     T *q;
     long long nn;
     double *out;
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm) const {
+    __device__ __forceinline__ void load(long long i, T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) in[c] = v[c * nn + i];
+    }
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const long long k = c * nn + i;
             const T qk = dir ? T(0) : val[c];
             q[k] = qk;
-            sm[0] += (double)v[k] * (double)qk;
+            sm[0] += (double)in[c] * (double)qk;
             sm[1] += (double)qk * (double)qk;
         }
     }
@@ -256,7 +287,9 @@ __global__ __launch_bounds__(BLOCK) void k_node(Grid g, Phys ph, const T *kap, c
 #pragma unroll
         for (int c = 0; c < NC; ++c) val[c] = T(0);
         if (!dir) node_value<DIM, KIND, MODE, T, TV>(g, ph, kap, x, v, Ax, eps, X, Y, Z, i, val);
-        epi.node(i, val, dir, sums);
+        T in[Epi::NIN * NC > 0 ? Epi::NIN * NC : 1];
+        epi.load(i, in);
+        epi.node(i, val, dir, sums, in);
     }
     if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
 }

@@ -2,7 +2,7 @@
 //
 // A block spans the whole x extent of the level: thread t owns the element
 // column ex = t (ceil(nx / 64) wavefronts, so every global access is a
-// coalesced row) and a tile of at most TROWS node rows in y and a chunk of
+// coalesced row) and a tile of a few node rows in y and a chunk of
 // node planes in z.  The block marches up in z with the two node planes
 // that bound the current element layer in LDS (state x, direction v,
 // coefficient e^m), one halo row on each side in y.  For every element
@@ -25,7 +25,13 @@
 
 namespace jfnk {
 
-constexpr int TROWS = 8;            // node rows per tile (register arrays)
+// node rows per tile (register arrays): 8; in FP64 only the residual and
+// the plain FD quotient without epilogue inputs keep 8 within the register
+// budget, the others take 4
+template <typename T, int MODE, class Epi> struct TileRows {
+    static constexpr bool wide = sizeof(T) == 4 || MODE == M_RESID || (MODE == M_FD_PLAIN && Epi::NIN == 0);
+    static constexpr int value = wide ? 8 : 4;
+};
 constexpr int TMAX_THREADS = 512;   // nx <= 512 elements per row
 
 struct TileArgs {
@@ -41,11 +47,12 @@ __device__ __forceinline__ int xcd_tile(int id, int nb) {
 }
 
 // Dynamic LDS of one block: two plane slots of x (T), e^m (T, INVCOEF) and
-// v (TV, FD modes), plus the TROWS x pitch hand-over buffer (T).
-template <typename T, typename TV, bool FD, bool INV>
+// v (TV, FD modes), plus the (tile rows) x pitch hand-over buffer (T).
+template <typename T, typename TV, int MODE, class Epi, bool INV>
 inline size_t tiled_lds_bytes(int pitch, int srows) {
+    constexpr bool FD = MODE != M_RESID;
     const size_t plane = (size_t)srows * pitch;
-    return 2 * plane * sizeof(T) * (INV ? 2 : 1) + (size_t)TROWS * pitch * sizeof(T) +
+    return 2 * plane * sizeof(T) * (INV ? 2 : 1) + (size_t)TileRows<T, MODE, Epi>::value * pitch * sizeof(T) +
            (FD ? 2 * plane * sizeof(TV) : 0);
 }
 
@@ -54,7 +61,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                                                         const T *Ax, FdStep fd, Epi epi, Red red, TileArgs ta) {
     constexpr bool FD = MODE != M_RESID;
     constexpr bool INV = KIND == JFNK_INVCOEF;
-    constexpr int R = TROWS;
+    constexpr int R = TileRows<T, MODE, Epi>::value;
     extern __shared__ __align__(16) unsigned char smem[];
     const int P = ta.pitch;
     const int plane = ta.srows * P;
@@ -205,43 +212,62 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 
     // iteration z evaluates element layer z (planes z, z+1 in LDS) and, from
     // z0 on, finishes node plane z; the first one only builds the carry.
+    // The epilogue inputs of plane z (and A(x) for the plain FD quotient)
+    // are read before the element work.  Node (nx, y0 + k) of the last
+    // column is finished by thread k.
+    constexpr int NIN = Epi::NIN > 0 ? Epi::NIN : 1;
+    constexpr bool PLAIN = MODE == M_FD_PLAIN;
     for (int z = z0 - 1; z < z1; ++z) {
-        if (z >= z0 && z + 2 <= z1) fetch(z + 2);
+        T pin[R][NIN], pax[R], qin[NIN], qax = T(0);
+        if (z >= z0) {
+            if (z + 2 <= z1) fetch(z + 2);
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                pax[k] = T(0);
+                if (k < rows && own_col) {
+                    const long long i = (long long)((z * g.NY + y0 + k) * g.NX + t);
+                    epi.load(i, pin[k]);
+                    if constexpr (PLAIN) pax[k] = Ax[i];
+                }
+            }
+            if (extra && t < rows) {
+                const long long i = (long long)((z * g.NY + y0 + t) * g.NX + g.nx);
+                epi.load(i, qin);
+                if constexpr (PLAIN) qax = Ax[i];
+            }
+        }
         layer(z);
         __syncthreads();
         if (z + 2 <= z1) store(z + 2);
         if (z >= z0) {
             const bool zd = zdir(z);
-#pragma unroll 1
-            for (int k = 0; k < rows; ++k) {
-                const int gy = y0 + k;
-                const bool yzd = zd || ydir(gy);
-                const int base = (z * g.NY + gy) * g.NX;
-                const T own = O[0];
 #pragma unroll
-                for (int j = 0; j < R - 1; ++j) O[j] = O[j + 1];
+            for (int k = 0; k < R; ++k) {
+                if (k >= rows) break;
+                const int gy = y0 + k;
                 if (own_col) {
-                    const int i = base + t;
-                    const bool dir = yzd || xdir_t;
+                    const long long i = (long long)((z * g.NY + gy) * g.NX + t);
+                    const bool dir = zd || ydir(gy) || xdir_t;
                     T val[1] = {T(0)};
                     if (!dir && !zero_fd) {
-                        T acc = own + xb[k * P + t];
-                        if constexpr (MODE == M_FD_PLAIN) acc = (acc - Ax[i]) * ie;
+                        T acc = O[k] + xb[k * P + t];
+                        if constexpr (PLAIN) acc = (acc - pax[k]) * ie;
                         val[0] = acc;
                     }
-                    epi.node(i, val, dir, sums);
+                    epi.node(i, val, dir, sums, pin[k]);
                 }
-                if (extra && t == nthr - 1) {     // node column nx: only element nx - 1 touches it
-                    const int i = base + g.nx;
-                    const bool dir = yzd || xdir_e;
-                    T val[1] = {T(0)};
-                    if (!dir && !zero_fd) {
-                        T acc = xb[k * P + g.nx];
-                        if constexpr (MODE == M_FD_PLAIN) acc = (acc - Ax[i]) * ie;
-                        val[0] = acc;
-                    }
-                    epi.node(i, val, dir, sums);
+            }
+            if (extra && t < rows) {
+                const int gy = y0 + t;
+                const long long i = (long long)((z * g.NY + gy) * g.NX + g.nx);
+                const bool dir = zd || ydir(gy) || xdir_e;
+                T val[1] = {T(0)};
+                if (!dir && !zero_fd) {
+                    T acc = xb[t * P + g.nx];
+                    if constexpr (PLAIN) acc = (acc - qax) * ie;
+                    val[0] = acc;
                 }
+                epi.node(i, val, dir, sums, qin);
             }
         }
         __syncthreads();

@@ -129,3 +129,56 @@ def test_edge_cases():
     u = to_dev(np.zeros(oracle_grid(w).node_shape))
     rep = api.jfnk_solve(ctx, u, None, None)
     assert rep['status'] != 'ok'
+
+
+def test_autograd_solve_gradients():
+    """JFNKSolve: d/dm and d/db of 1/2 ||u - u_obs||^2 by torch autograd
+    against the oracle's adjoint gradient and adjoint state."""
+    w = W.scaled('invcoef3d-128', (16, 16, 16), nlevels=3)
+    g = oracle_grid(w)
+    b = _load(w)
+    m = W.matern_field(w['n'], w['h'], 3)
+    m_obs = W.matern_field(w['n'], w['h'], 4)
+    u_ref, _ = _oracle_solve(w, b, m)
+    uo_ref, _ = _oracle_solve(w, b, m_obs)
+    grad_ref, lam_ref, _, ok = OA.gradient(oracle_problem(w), g, w['nlevels'], u_ref, m, uo_ref,
+                                           oracle_mg_options(w))
+    assert ok
+    ctx = make_ctx(w, newton_rtol=1e-12)
+    md = to_dev(m).requires_grad_(True)
+    bd = to_dev(b).requires_grad_(True)
+    u = api.JFNKSolve.apply(md, bd, ctx, None, 1e-12)
+    assert rel(to_np(u), u_ref) < 1e-8
+    d = u - to_dev(uo_ref)
+    d = d.masked_fill(to_dev(g.dirichlet_mask()), 0.0)
+    loss = 0.5 * (d * d).sum()
+    loss.backward()
+    assert rel(to_np(md.grad), grad_ref) < 1e-8
+    assert rel(to_np(bd.grad), lam_ref) < 1e-8
+
+
+def test_load_steps_neohooke():
+    """Load stepping: the GPU increments reach the oracle's load-stepped root.
+    Each increment stops at 1e-10 relative: the FP64 rounding floor of the
+    Neo-Hookean residual (about 4e-16 absolute here) sits near 1e-11 of the
+    full load's initial residual, so smaller increments cannot reach 1e-11."""
+    w = small('neohooke-solve')
+    b = _load(w)
+    g = oracle_grid(w)
+    rtol = 1e-10
+    ref, reps = ON.load_steps(oracle_problem(w), g, w['nlevels'], np.zeros((3,) + g.node_shape), b, 3,
+                              mg_opts=oracle_mg_options(w), opts=ON.NewtonOptions(rtol=rtol))
+    assert all(r.status == 'ok' for _, r in reps)
+    ctx = make_ctx(w, newton_rtol=rtol)
+    u = to_dev(np.zeros_like(ref))
+    rep = api.jfnk_solve_steps(ctx, u, 3, None, to_dev(b))
+    assert rep['status'] == 'ok', rep
+    assert rel(to_np(u), ref) < 1e-8
+    assert rep['alpha_hist'][-1] == 1.0
+    # one increment equals a plain solve
+    u1 = to_dev(np.zeros_like(ref))
+    rep1 = api.jfnk_solve_steps(ctx, u1, 1, None, to_dev(b))
+    u2 = to_dev(np.zeros_like(ref))
+    rep2 = api.jfnk_solve(ctx, u2, None, to_dev(b))
+    assert rep1['status'] == rep2['status'] == 'ok'
+    assert torch.equal(u1, u2)
