@@ -60,10 +60,11 @@ template <typename T> __device__ __forceinline__ T hw_div(T a, T b) { return a /
 template <> __device__ __forceinline__ float hw_div<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // (delta^2 + s)^e for the exponents the p-Laplacian needs
-template <typename T>
+// PF = 3: the exponent p = 3 is known at compile time; PF = 0: read p.
+template <typename T, int PF = 0>
 __device__ __forceinline__ T plap_pow(T base, double p, int which) {
     // which 0: (p-2)/2, 1: p/2, 2: (p-4)/2
-    if (p == 3.0) {
+    if (PF == 3 || p == 3.0) {
         T r = hw_sqrt(base);
         return which == 0 ? r : (which == 1 ? base * r : hw_div(T(1), r));
     }
@@ -75,7 +76,7 @@ __device__ __forceinline__ T plap_pow(T base, double p, int which) {
 // ---------------------------------------------------------------------------
 // scalar kinds: r[a] for one element.  w: state corners, kap: e^{m} corners
 // ---------------------------------------------------------------------------
-template <int DIM, int KIND, typename T>
+template <int DIM, int KIND, typename T, int PF = 0>
 __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys &ph, T h, T *r) {
     constexpr int NV = Cell<DIM>::NV;
     T Ku[NV];
@@ -106,7 +107,7 @@ __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys
         // s = u^T K_e u / |e| = quad * h^(d-2) / h^d = quad / h^2
         T s = quad / (h * h);
         T d2 = T(ph.a1) * T(ph.a1);
-        T k = plap_pow<T>(d2 + s, ph.a0, 0) * hs;
+        T k = plap_pow<T, PF>(d2 + s, ph.a0, 0) * hs;
 #pragma unroll
         for (int a = 0; a < NV; ++a) r[a] = k * Ku[a];
     } else {  // INVCOEF
@@ -157,7 +158,7 @@ __device__ __forceinline__ T elem_scalar_energy(const T *w, const Phys &ph, T h)
 // the same quotient as Sec. 1 with the same eps; only the rounding differs
 // (no cancellation between the two residual evaluations, which in FP32
 // destroys the action on smooth directions).
-template <int DIM, int KIND, typename T>
+template <int DIM, int KIND, typename T, int PF = 0>
 __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *kap, T eps, const Phys &ph,
                                                T h, T *q) {
     constexpr int NV = Cell<DIM>::NV;
@@ -205,7 +206,7 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
         const T bx = T(ph.a1) * T(ph.a1) + qxx * ih2;
         const T dsq = (T(2) * qxv + eps * qvv) * ih2;        // (s_w - s_x) / eps
         const T bw = bx + eps * dsq;
-        if (ph.a0 == 3.0) {
+        if (PF == 3 || ph.a0 == 3.0) {
             const T kx = hw_sqrt(bx);
             kw = hw_sqrt(bw);
             dk = hw_div(dsq, kw + kx);

@@ -56,7 +56,8 @@ inline size_t tiled_lds_bytes(int pitch, int srows) {
            (FD ? 2 * plane * sizeof(TV) : 0);
 }
 
-template <int KIND, int MODE, typename T, typename TV, class Epi>
+// PF = 3: p-Laplacian with p = 3 fixed at compile time (no exponent branches)
+template <int KIND, int MODE, typename T, typename TV, class Epi, int PF = 0>
 __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T *kap, const T *x, const TV *v,
                                                         const T *Ax, FdStep fd, Epi epi, Red red, TileArgs ta) {
     constexpr bool FD = MODE != M_RESID;
@@ -94,27 +95,47 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     auto zdir = [&](int gz) { return ((g.dir & JFNK_FACE_ZLO) && gz == 0) || ((g.dir & JFNK_FACE_ZHI) && gz == g.nz); };
 
     // ---- plane fetch (global -> registers) and store (registers -> LDS) ----
+    // Loads use clamped indices and are always issued; values outside the
+    // grid (or on Dirichlet nodes, for v) are replaced by zero afterwards.
+    const int tc = t < g.NX ? t : g.NX - 1;
     T px[R + 2], pk[R + 2], qx = T(0), qk = T(0);
     TV pv[R + 2], qv = TV(0);
     auto fetch = [&](int pz) {
-        const bool zin = pz >= 0 && pz < g.NZ;
+        const int pzc = pz < 0 ? 0 : (pz >= g.NZ ? g.NZ - 1 : pz);
+        const bool zin = pz == pzc;
         const bool zd = zdir(pz);
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
             const int gy = y0 - 1 + r;
-            const bool in = zin && r < rows + 2 && gy >= 0 && gy < g.NY && own_col;
-            const int idx = (pz * g.NY + gy) * g.NX + t;
-            px[r] = in ? x[idx] : T(0);
-            if constexpr (FD) pv[r] = (in && !(xdir_t || zd || ydir(gy))) ? v[idx] : TV(0);
-            if constexpr (INV) pk[r] = in ? kap[idx] : T(0);
+            const int gyc = gy < 0 ? 0 : (gy >= g.NY ? g.NY - 1 : gy);
+            const bool in = zin && gy == gyc && own_col;
+            const int idx = (pzc * g.NY + gyc) * g.NX + tc;
+            const T xv = x[idx];
+            px[r] = in ? xv : T(0);
+            if constexpr (FD) {
+                const TV vv = v[idx];
+                pv[r] = (in && !(xdir_t || zd || ydir(gy))) ? vv : TV(0);
+            }
+            if constexpr (INV) {
+                const T kv = kap[idx];
+                pk[r] = in ? kv : T(0);
+            }
         }
         if (extra) {       // column nx, row t
             const int gy = y0 - 1 + t;
-            const bool in = zin && t < rows + 2 && gy >= 0 && gy < g.NY;
-            const int idx = (pz * g.NY + gy) * g.NX + g.nx;
-            qx = in ? x[idx] : T(0);
-            if constexpr (FD) qv = (in && !(xdir_e || zd || ydir(gy))) ? v[idx] : TV(0);
-            if constexpr (INV) qk = in ? kap[idx] : T(0);
+            const int gyc = gy < 0 ? 0 : (gy >= g.NY ? g.NY - 1 : gy);
+            const bool in = zin && gy == gyc && t < rows + 2;
+            const int idx = (pzc * g.NY + gyc) * g.NX + g.nx;
+            const T xv = x[idx];
+            qx = in ? xv : T(0);
+            if constexpr (FD) {
+                const TV vv = v[idx];
+                qv = (in && !(xdir_e || zd || ydir(gy))) ? vv : TV(0);
+            }
+            if constexpr (INV) {
+                const T kv = kap[idx];
+                qk = in ? kv : T(0);
+            }
         }
     };
     auto store = [&](int pz) {
@@ -137,12 +158,12 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     };
 
     // ---- element layer ez, walked row by row --------------------------------
-    // The node rows of the tile pass through two register FIFOs of depth R:
-    // C0/C1 hold the contributions of the layer below to node columns t and
-    // t + 1 (the carry), O the finished value of column t.  Every walk
-    // shifts both exactly R times, so after it C holds this layer's carry
-    // into the plane above and O[k] the value of node row k (the part for
-    // column t + 1 goes to the hand-over buffer).
+    // C0/C1[k]: contributions of the layer below to node row y0 + k, columns
+    // t and t + 1 (the carry); O[k]: the finished value of column t.  The walk
+    // over the element rows is unrolled, so all indices are compile-time; a
+    // row k is finished when element row k + 1 is done, and its carry slot
+    // then takes this layer's contribution to the plane above.  The part for
+    // column t + 1 goes to the hand-over buffer.
     T C0[R], C1[R], O[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) { C0[k] = T(0); C1[k] = T(0); O[k] = T(0); }
@@ -162,12 +183,13 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         };
         if (lz) row(0, cx, cv, ck);
         T pS0 = T(0), pS1 = T(0), pN0 = T(0), pN1 = T(0);
-#pragma unroll 1
+#pragma unroll
         for (int re = 0; re <= R; ++re) {
+            if (re > rows) break;
             T r8[1][8];
 #pragma unroll
             for (int a = 0; a < 8; ++a) r8[0][a] = T(0);
-            if (lz && re <= rows) {
+            if (lz) {
                 T ux[4], uk[4];
                 TV uv[4];
 #pragma unroll
@@ -182,19 +204,18 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                     const T kk[8] = {ck[0], ck[1], uk[0], uk[1], ck[2], ck[3], uk[2], uk[3]};
 #pragma unroll
                     for (int a = 0; a < 8; ++a) { ve[0][a] = (T)vv[a]; kp[a] = kk[a]; }
-                    elem_eval<3, KIND, MODE, T, 1, 8>(xe, ve, kp, e, ph, h, r8);
+                    elem_eval<3, KIND, MODE, T, 1, 8, PF>(xe, ve, kp, e, ph, h, r8);
                 }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { cx[c] = ux[c]; cv[c] = uv[c]; ck[c] = uk[c]; }
             }
             if (re >= 1) {     // node row re - 1 is complete for this layer
-                const T t0 = C0[0] + (pS0 + r8[0][0]);
-                const T t1 = C1[0] + (pS1 + r8[0][1]);
-                const T n0 = pN0 + r8[0][4], n1 = pN1 + r8[0][5];
-                if (own_elem && re - 1 < rows) xb[(re - 1) * P + t + 1] = t1;
-#pragma unroll
-                for (int k = 0; k < R - 1; ++k) { C0[k] = C0[k + 1]; C1[k] = C1[k + 1]; O[k] = O[k + 1]; }
-                C0[R - 1] = n0; C1[R - 1] = n1; O[R - 1] = t0;
+                const int k = re - 1;
+                O[k] = C0[k] + (pS0 + r8[0][0]);
+                const T t1 = C1[k] + (pS1 + r8[0][1]);
+                C0[k] = pN0 + r8[0][4];
+                C1[k] = pN1 + r8[0][5];
+                if (own_elem && k < rows) xb[k * P + t + 1] = t1;
             }
             pS0 = r8[0][2]; pS1 = r8[0][3]; pN0 = r8[0][6]; pN1 = r8[0][7];
         }
@@ -221,17 +242,17 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         T pin[R][NIN], pax[R], qin[NIN], qax = T(0);
         if (z >= z0) {
             if (z + 2 <= z1) fetch(z + 2);
+            // clamped row and column: always a valid node, unused where out of the tile
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                pax[k] = T(0);
-                if (k < rows && own_col) {
-                    const long long i = (long long)((z * g.NY + y0 + k) * g.NX + t);
-                    epi.load(i, pin[k]);
-                    if constexpr (PLAIN) pax[k] = Ax[i];
-                }
+                const int kc = k < rows ? k : rows - 1;
+                const long long i = (long long)((z * g.NY + y0 + kc) * g.NX + tc);
+                epi.load(i, pin[k]);
+                pax[k] = PLAIN ? Ax[i] : T(0);
             }
-            if (extra && t < rows) {
-                const long long i = (long long)((z * g.NY + y0 + t) * g.NX + g.nx);
+            if (extra) {
+                const int kc = t < rows ? t : rows - 1;
+                const long long i = (long long)((z * g.NY + y0 + kc) * g.NX + g.nx);
                 epi.load(i, qin);
                 if constexpr (PLAIN) qax = Ax[i];
             }
