@@ -25,12 +25,13 @@
 
 namespace jfnk {
 
-// node rows per tile (register arrays): 8; in FP64 only the residual and
-// the plain FD quotient without epilogue inputs keep 8 within the register
-// budget, the others take 4
+// node rows per tile (register arrays).  FP32: 4, which keeps the kernel
+// under 128 VGPRs (4 waves per SIMD); measured faster than 3, 5, 6 or 8 at
+// 256^3 despite the larger y halo.  FP64: 8 for the residual and the plain
+// FD quotient without epilogue inputs, 4 for the others (register budget).
 template <typename T, int MODE, class Epi> struct TileRows {
-    static constexpr bool wide = sizeof(T) == 4 || MODE == M_RESID || (MODE == M_FD_PLAIN && Epi::NIN == 0);
-    static constexpr int value = wide ? 8 : 4;
+    static constexpr bool wide = MODE == M_RESID || (MODE == M_FD_PLAIN && Epi::NIN == 0);
+    static constexpr int value = (sizeof(T) == 8 && wide) ? 8 : 4;
 };
 constexpr int TMAX_THREADS = 512;   // nx <= 512 elements per row
 
