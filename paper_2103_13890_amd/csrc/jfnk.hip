@@ -408,7 +408,8 @@ ChebCoef cheb_coef(jfnk_ctx *c, int l) {
 // nu Chebyshev steps on J_l s = b; the result goes to out (||out||^2 -> out_n2).
 // zero: start from s = 0.  Otherwise ||s||^2 must be in the level's L_S slot.
 template <typename T>
-void chebyshev(jfnk_ctx *c, int l, const T *b, T *s, int nu, bool zero, T *out, double *out_n2) {
+void chebyshev(jfnk_ctx *c, int l, const T *b, T *s, int nu, bool zero, T *out, double *out_n2,
+               const double *b_n2 = nullptr) {
     Level &L = c->lev[l];
     const Grid &g = L.g;
     const int nc = c->nc;
@@ -425,18 +426,42 @@ void chebyshev(jfnk_ctx *c, int l, const T *b, T *s, int nu, bool zero, T *out, 
     const ChebCoef k = cheb_coef(c, l);
     double rho = 1.0 / k.sigma;
     const bool fine = (l == c->L);
-    if (zero) {
+    // the steps k = 0 .. nu-2 each cost one J d_k; the last update s += d_{nu-1}
+    // none.  From s = 0 the first step runs on the direction b itself (||b||^2
+    // in b_n2, or computed here); the last step with a J d writes s + d + d'.
+    const bool fuse_first = zero && nu >= 3;
+    int first_it = 0;
+    if (fuse_first) {
+        if (!b_n2) {
+            vec_dot<T, T>(c->ex, g.nn * nc, b, b, lslot(c, l, L_B));
+            b_n2 = lslot(c, l, L_B);
+        }
+        const double rn = 1.0 / (2.0 * k.sigma - rho);
+        TimeScope ts(c, fine ? JFNK_TIMER_CHEB_FINE : JFNK_TIMER_COUNT);
+        op_cheb_first<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), b, lslot(c, l, L_NUM),
+                         b_n2, P<T>(L.r), s, P<T>(L.d[1]), 1.0 / k.theta, rn * rho, 2.0 * rn / k.delta,
+                         lslot(c, l, L_D1));
+        c->ge[l] += 1;
+        rho = rn;
+        first_it = 1;
+    } else if (zero) {
         vec_cheb_zero<T>(c->ex, g, nc, b, P<T>(L.r), P<T>(L.d[0]), s, 1.0 / k.theta, lslot(c, l, L_D0));
     } else {
         op_cheb_init<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), s, lslot(c, l, L_NUM),
                         lslot(c, l, L_S), b, P<T>(L.r), P<T>(L.d[0]), 1.0 / k.theta, lslot(c, l, L_D0));
         c->ge[l] += 1;
     }
-    int cur = 0;
-    for (int it = 0; it < nu - 1; ++it) {
+    int cur = first_it;
+    for (int it = first_it; it < nu - 1; ++it) {
         const double rn = 1.0 / (2.0 * k.sigma - rho);
         const double c1 = rn * rho, c2 = 2.0 * rn / k.delta;
         TimeScope ts(c, fine ? JFNK_TIMER_CHEB_FINE : JFNK_TIMER_COUNT);
+        if (it == nu - 2) {
+            op_cheb_last<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), CP<T>(L.d[cur]),
+                            lslot(c, l, L_NUM), lslot(c, l, cur ? L_D1 : L_D0), CP<T>(L.r), s, out, c1, c2, out_n2);
+            c->ge[l] += 1;
+            return;
+        }
         op_cheb_step<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), CP<T>(L.d[cur]),
                         lslot(c, l, L_NUM), lslot(c, l, cur ? L_D1 : L_D0), P<T>(L.r), s, P<T>(L.d[1 - cur]), c1,
                         c2, lslot(c, l, cur ? L_D0 : L_D1));
@@ -447,7 +472,9 @@ void chebyshev(jfnk_ctx *c, int l, const T *b, T *s, int nu, bool zero, T *out, 
     vec_add<T>(c->ex, g, nc, s, CP<T>(L.d[cur]), out, out_n2);
 }
 
-template <typename T> void vcycle(jfnk_ctx *c, int l, const T *b, T *s_out, double *s_out_n2) {
+// b_n2: device slot holding ||b||^2, or nullptr (then computed where needed)
+template <typename T>
+void vcycle(jfnk_ctx *c, int l, const T *b, T *s_out, double *s_out_n2, const double *b_n2 = nullptr) {
     Level &L = c->lev[l];
     const int nc = c->nc;
     if (l == 0) {
@@ -465,14 +492,14 @@ template <typename T> void vcycle(jfnk_ctx *c, int l, const T *b, T *s_out, doub
     }
     T *s = P<T>(L.s);
     // pre-smoothing from s = 0; s and ||s||^2 (L_S) materialised
-    chebyshev<T>(c, l, b, s, c->opt.nu_pre, true, s, lslot(c, l, L_S));
+    chebyshev<T>(c, l, b, s, c->opt.nu_pre, true, s, lslot(c, l, L_S), b_n2);
     // r_{l-1} = R (b - J s)
     op_resid_jv<T>(c->ex, mg_mode(c), L.g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), s, lslot(c, l, L_NUM),
                    lslot(c, l, L_S), b, P<T>(L.t));
     c->ge[l] += 1;
     Level &C = c->lev[l - 1];
     tr_restrict<T>(c->ex, L.g, C.g, nc, CP<T>(L.t), P<T>(C.b), lslot(c, l - 1, L_B));
-    vcycle<T>(c, l - 1, CP<T>(C.b), P<T>(C.s), nullptr);
+    vcycle<T>(c, l - 1, CP<T>(C.b), P<T>(C.s), nullptr, lslot(c, l - 1, L_B));
     // s += I c, ||s||^2 for the post-smoother's first FD step
     tr_prolong_add<T>(c->ex, L.g, C.g, nc, CP<T>(C.s), s, lslot(c, l, L_S));
     chebyshev<T>(c, l, b, s, c->opt.nu_post, false, s_out, s_out_n2);
@@ -485,8 +512,10 @@ template <typename T> void precondition(jfnk_ctx *c, const double *v, T *z) {
     if (std::is_same<T, double>::value) {
         b = (const T *)v;
     } else {
-        vec_cast<double, T>(c->ex, L.g, c->nc, v, P<T>(L.b), nullptr);
+        vec_cast<double, T>(c->ex, L.g, c->nc, v, P<T>(L.b), lslot(c, c->L, L_B));
         b = CP<T>(L.b);
+        vcycle<T>(c, c->L, b, z, slot(c, S_ZN2), lslot(c, c->L, L_B));
+        return;
     }
     vcycle<T>(c, c->L, b, z, slot(c, S_ZN2));
 }

@@ -38,6 +38,18 @@ template <typename T>
 void op_cheb_step(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
                   const T *d, const double *num, const double *vn2, T *r, T *s, T *dn, double c1, double c2,
                   double *dn_nrm2);
+// first Chebyshev step from s = 0 with the direction b (||b||^2 in vn2):
+// s = b / theta, r = b - (J b) / theta, dn = c1 s + c2 r; ||dn||^2 -> dn_nrm2
+template <typename T>
+void op_cheb_first(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
+                   const T *b, const double *num, const double *vn2, T *r, T *s, T *dn, double inv_theta, double c1,
+                   double c2, double *dn_nrm2);
+// last Chebyshev step with d_k: sout = s + d_k + (c1 d_k + c2 (r - J d_k));
+// ||sout||^2 -> s_nrm2 (nullable).  sout may alias s.
+template <typename T>
+void op_cheb_last(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
+                  const T *d, const double *num, const double *vn2, const T *r, const T *s, T *sout, double c1,
+                  double c2, double *s_nrm2);
 // Chebyshev start from s: r = b - J s, d = r / theta
 template <typename T>
 void op_cheb_init(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,

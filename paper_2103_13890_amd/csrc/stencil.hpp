@@ -123,6 +123,84 @@ template <typename T, int NC> struct EpiCheb {
     __device__ void operator()(const double *t) const { out[0] = t[0]; }
 };
 
+// First Chebyshev step from s = 0, with the direction b instead of
+// d_0 = b / theta: the FD quotient is homogeneous in its direction (the step
+// eps = num / ||v|| makes eps v the same vector), so J d_0 = (J b) / theta.
+// val = J b;  s_1 = b / theta;  r_1 = b - val / theta;  d_1 = c1 s_1 + c2 r_1;
+// ||d_1||^2 -> out
+template <typename T, int NC> struct EpiChebFirst {
+    static constexpr int NS = 1;
+    static constexpr int NCOMP = NC;
+    static constexpr int NIN = 1;
+    const T *b;
+    T *r, *s, *dn;
+    T inv_theta, c1, c2;
+    long long nn;
+    double *out;
+    __device__ __forceinline__ void load(long long i, T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) in[c] = b[c * nn + i];
+    }
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            if (dir) {
+                r[k] = T(0); s[k] = T(0); dn[k] = T(0);
+                continue;
+            }
+            const T d0 = in[c] * inv_theta;
+            s[k] = d0;
+            const T rk = in[c] - val[c] * inv_theta;
+            r[k] = rk;
+            const T dnew = c1 * d0 + c2 * rk;
+            dn[k] = dnew;
+            sm[0] += (double)dnew * (double)dnew;
+        }
+    }
+    __device__ void operator()(const double *t) const { out[0] = t[0]; }
+};
+
+// Last Chebyshev step k, q = J d_k: r' = r - q, d_{k+1} = c1 d_k + c2 r',
+// and the polynomial's final update s_out = s + d_k + d_{k+1} (r' and
+// d_{k+1} are not kept); ||s_out||^2 -> out (nullable)
+template <typename T, int NC> struct EpiChebLast {
+    static constexpr int NS = 1;
+    static constexpr int NCOMP = NC;
+    static constexpr int NIN = 3;
+    const T *d, *r, *s;
+    T *sout;
+    T c1, c2;
+    long long nn;
+    double *out;
+    __device__ __forceinline__ void load(long long i, T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            in[3 * c] = d[k];
+            in[3 * c + 1] = r[k];
+            in[3 * c + 2] = s[k];
+        }
+    }
+    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const long long k = c * nn + i;
+            if (dir) {
+                sout[k] = T(0);
+                continue;
+            }
+            const T dk = in[3 * c];
+            const T rk = in[3 * c + 1] - val[c];
+            const T dnew = c1 * dk + c2 * rk;
+            const T so = (in[3 * c + 2] + dk) + dnew;
+            sout[k] = so;
+            sm[0] += (double)so * (double)so;
+        }
+    }
+    __device__ void operator()(const double *t) const { if (out) out[0] = t[0]; }
+};
+
 // t = b - J s  (the residual restricted in Algorithm 1)
 template <typename T, int NC> struct EpiResidJv {
     static constexpr int NS = 0;

@@ -492,10 +492,53 @@ __global__ void k_restrict(Grid gf, Grid gc, int nc, const T *rf, T *rc, Red red
     }
     if (out) block_partials<1>(sm, red);
 }
+// 3D, one component: the 27 fine neighbours of a coarse node with weights
+// (1/2, 1, 1/2) per axis, as straight-line code; indices are clamped into the
+// grid and the weight of a clamped neighbour is 0.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_restrict3(Grid gf, Grid gc, const T *rf, T *rc, Red red, double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, gc.nn) {
+        int cx, cy, cz;
+        node_coords(gc, i, cx, cy, cz);
+        T acc = T(0);
+        if (!is_dirichlet(gc, cx, cy, cz)) {
+            int ix[3], iy[3], iz[3];
+            T wx[3], wy[3], wz[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int fx = 2 * cx + d - 1, fy = 2 * cy + d - 1, fz = 2 * cz + d - 1;
+                const T w = d == 1 ? T(1) : T(0.5);
+                wx[d] = (fx >= 0 && fx < gf.NX) ? w : T(0);
+                wy[d] = (fy >= 0 && fy < gf.NY) ? w : T(0);
+                wz[d] = (fz >= 0 && fz < gf.NZ) ? w : T(0);
+                ix[d] = min(max(fx, 0), gf.NX - 1);
+                iy[d] = min(max(fy, 0), gf.NY - 1);
+                iz[d] = min(max(fz, 0), gf.NZ - 1);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                T pz = T(0);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const T *row = rf + ((long long)iz[a] * gf.NY + iy[b]) * gf.NX;
+                    const T px = wx[0] * row[ix[0]] + wx[1] * row[ix[1]] + wx[2] * row[ix[2]];
+                    pz += wy[b] * px;
+                }
+                acc += wz[a] * pz;
+            }
+        }
+        rc[i] = acc;
+        sm[0] += (double)acc * (double)acc;
+    }
+    if (out) block_partials<1>(sm, red);
+}
+
 template <typename T>
 void tr_restrict(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *rf, T *rc, double *nrm2) {
     const int nb = vblocks(gc.nn);
-    k_restrict<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, rf, rc, ex.red, nrm2);
+    if (gf.dim == 3 && nc == 1) k_restrict3<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, rf, rc, ex.red, nrm2);
+    else k_restrict<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, rf, rc, ex.red, nrm2);
     if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void tr_restrict<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
@@ -535,10 +578,46 @@ __global__ void k_prolong_add(Grid gf, Grid gc, int nc, const T *cc, T *sf, Red 
     }
     if (out) block_partials<1>(sm, red);
 }
+// 3D, one component: the (up to) 8 coarse corners of the fine node's
+// coarse cell as straight-line code.  On an even fine coordinate both coarse
+// indices coincide and the weights are (1, 0); on an odd one (1/2, 1/2).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_prolong_add3(Grid gf, Grid gc, const T *cc, T *sf, Red red,
+                                                        double *out) {
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, gf.nn) {
+        int fx, fy, fz;
+        node_coords(gf, i, fx, fy, fz);
+        T sv = T(0);
+        if (!is_dirichlet(gf, fx, fy, fz)) {
+            const int X[2] = {fx >> 1, (fx + 1) >> 1}, Y[2] = {fy >> 1, (fy + 1) >> 1}, Z[2] = {fz >> 1, (fz + 1) >> 1};
+            const T wx[2] = {(fx & 1) ? T(0.5) : T(1), (fx & 1) ? T(0.5) : T(0)};
+            const T wy[2] = {(fy & 1) ? T(0.5) : T(1), (fy & 1) ? T(0.5) : T(0)};
+            const T wz[2] = {(fz & 1) ? T(0.5) : T(1), (fz & 1) ? T(0.5) : T(0)};
+            T v = T(0);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                T py = T(0);
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const T *row = cc + ((long long)Z[a] * gc.NY + Y[b]) * gc.NX;
+                    py += wy[b] * (wx[0] * row[X[0]] + wx[1] * row[X[1]]);
+                }
+                v += wz[a] * py;
+            }
+            sv = sf[i] + v;
+        }
+        sf[i] = sv;
+        sm[0] += (double)sv * (double)sv;
+    }
+    if (out) block_partials<1>(sm, red);
+}
+
 template <typename T>
 void tr_prolong_add(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *cc, T *sf, double *nrm2) {
     const int nb = vblocks(gf.nn);
-    k_prolong_add<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, cc, sf, ex.red, nrm2);
+    if (gf.dim == 3 && nc == 1) k_prolong_add3<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, cc, sf, ex.red, nrm2);
+    else k_prolong_add<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, cc, sf, ex.red, nrm2);
     if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 template void tr_prolong_add<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
