@@ -315,6 +315,8 @@ def main():
                    'discretisation': 'Q1, element-mean coefficient'},
         'ok': ok32, 'newton_iters': reps32[-1]['newton_iters'], 'krylov_iters': reps32[-1]['linear_iters'],
         'ge_effective': ge32, 'final_rel_residual': reps32[-1]['fnorm'] / reps32[-1]['fnorm0'],
+        'coarse': {'calls': reps32[-1]['coarse_calls'], 'cg_iters': reps32[-1]['coarse_iters'],
+                   'neg_curv': reps32[-1]['neg_curv']},
         'roofline': roofline, 'kernel_shares': kernel_shares, 'cpu_baseline': cpu,
     }
     out.update(extra)

@@ -26,24 +26,69 @@ template <int DIM, int KIND, int MODE, typename T>
 __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap, const T *x, const T *Ax,
                                                    const double *num, const T *b, T *s, T *work, CoarseArgs ca) {
     constexpr int NC = (KIND == JFNK_NEOHOOKE) ? 3 : 1;
+    constexpr int NV = Cell<DIM>::NV;
     const long long nn = g.nn, n = nn * NC;
-    T *r = work, *p = work + n, *q = work + 2 * n;
+    const long long ne = (long long)g.nx * g.ny * (DIM == 3 ? g.nz : 1);
+    // r, p, q, then the element contributions ew[(c * ne + e) * NV + a]
+    T *r = work, *p = work + n, *q = work + 2 * n, *ew = work + 3 * n;
     const double epsn = *num;
+    const T h = (T)g.h;
+    const double rnx = 1.0 / g.nx, rny = 1.0 / g.ny;
 
-    // q = (J - shift I) v via the FD quotient; returns v.v
-    auto apply = [&](const T *v, double shift) -> double {
-        double vv = 0.0;
-        NODE_LOOP(i, n) vv += (double)v[i] * (double)v[i];
-        vv = cg_bsum(vv);
+    // q = (J - shift I) v via the FD quotient, given vv = v.v.  Every element
+    // is evaluated once (its corner contributions go to ew); each node then
+    // sums the contributions of its adjacent elements in a fixed order.
+    auto apply = [&](const T *v, double vv, double shift) {
         const double eps = vv > 0.0 ? epsn / sqrt(vv) : 0.0;
+        const T e = (T)eps;
+        const bool zero_fd = eps == 0.0;
+        NODE_LOOP(el, ne) {
+            unsigned qq, rr, q2, r2;
+            udivmod((unsigned)el, (unsigned)g.nx, rnx, qq, rr);
+            udivmod(qq, (unsigned)g.ny, rny, q2, r2);
+            const int ex = (int)rr, ey = DIM == 3 ? (int)r2 : (int)qq, ez = DIM == 3 ? (int)q2 : 0;
+            T xe[NC][NV], ve[NC][NV], kp[NV], r8[NC][NV];
+#pragma unroll
+            for (int a = 0; a < NV; ++a) {
+                const int ax = ex + (a & 1), ay = ey + ((a >> 1) & 1), az = ez + ((a >> 2) & 1);
+                const long long j = node_index(g, ax, ay, az);
+                const bool dj = is_dirichlet(g, ax, ay, az);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    xe[c][a] = x[c * nn + j];
+                    ve[c][a] = dj ? T(0) : v[c * nn + j];
+                }
+                kp[a] = (KIND == JFNK_INVCOEF) ? kap[j] : T(0);
+            }
+            if (!zero_fd) elem_eval<DIM, KIND, MODE, T, NC, NV>(xe, ve, kp, e, ph, h, r8);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int a = 0; a < NV; ++a) ew[(c * ne + el) * NV + a] = zero_fd ? T(0) : r8[c][a];
+        }
+        __syncthreads();
         NODE_LOOP(i, nn) {
             int X, Y, Z;
             node_coords(g, i, X, Y, Z);
+            const bool dir = is_dirichlet(g, X, Y, Z);
             T val[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) val[c] = T(0);
-            const bool dir = is_dirichlet(g, X, Y, Z);
-            if (!dir) node_value<DIM, KIND, MODE, T, T>(g, ph, kap, x, v, Ax, eps, X, Y, Z, i, val);
+            if (!dir && !zero_fd) {
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {   // the element whose corner a is this node
+                    const int ex = X - (a & 1), ey = Y - ((a >> 1) & 1), ez = DIM == 3 ? Z - ((a >> 2) & 1) : 0;
+                    if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny) continue;
+                    if (DIM == 3 && (ez < 0 || ez >= g.nz)) continue;
+                    const long long el = ((long long)ez * g.ny + ey) * g.nx + ex;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) val[c] += ew[(c * ne + el) * NV + a];
+                }
+                if constexpr (MODE == M_FD_PLAIN) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) val[c] = (val[c] - Ax[c * nn + i]) * (T)(1.0 / eps);
+                }
+            }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const long long k = c * nn + i;
@@ -51,7 +96,6 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
             }
         }
         __syncthreads();
-        return vv;
     };
 
     double bb = 0.0;
@@ -66,7 +110,9 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
 
     auto cg = [&](double shift) -> double {
         if (s_nonzero) {
-            apply(s, shift);
+            double ss = 0.0;
+            NODE_LOOP(i, n) ss += (double)s[i] * (double)s[i];
+            apply(s, cg_bsum(ss), shift);
             ++fd;
             NODE_LOOP(i, n) r[i] = b[i] - q[i];
         } else {
@@ -79,8 +125,9 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
         }
         rr = cg_bsum(rr);
         if (sqrt(rr) <= tol) return 0.0;
+        double pp = rr;             // ||p||^2, carried from the p update
         for (int it = 1; it <= ca.maxit; ++it) {
-            const double pp = apply(p, shift);
+            apply(p, pp, shift);
             ++fd;
             ++iters;
             double pq = 0.0;
@@ -100,8 +147,13 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
             rn = cg_bsum(rn);
             if (sqrt(rn) <= tol) return 0.0;
             const T beta = (T)(rn / rr);
-            NODE_LOOP(i, n) p[i] = r[i] + beta * p[i];
-            __syncthreads();
+            double pn = 0.0;
+            NODE_LOOP(i, n) {
+                const T pi = r[i] + beta * p[i];
+                p[i] = pi;
+                pn += (double)pi * (double)pi;
+            }
+            pp = cg_bsum(pn);
             rr = rn;
         }
         return 0.0;
@@ -127,9 +179,154 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
     }
 }
 
+// The same solver for a scalar coarse level with at most CBLOCK nodes: thread
+// i owns node i and keeps its entries of r, p, q, s, b in registers; the
+// state x, e^m, the direction being applied and the element contributions
+// live in LDS, so an iteration touches no global memory.
+template <int DIM, int KIND, int MODE, typename T>
+__global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const T *kap, const T *x, const T *Ax,
+                                                         const double *num, const T *b, T *s_out, CoarseArgs ca) {
+    constexpr int NV = Cell<DIM>::NV;
+    constexpr bool INV = KIND == JFNK_INVCOEF;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nn = (int)g.nn;
+    const int ne = g.nx * g.ny * (DIM == 3 ? g.nz : 1);
+    T *sx = (T *)smem, *sv = sx + nn, *sk = sv + nn, *ew = sk + (INV ? nn : 0);
+    const int i = threadIdx.x;
+    const bool act = i < nn;
+    const double epsn = *num;
+    const T h = (T)g.h;
+    int X = 0, Y = 0, Z = 0;
+    bool dir = true;
+    T bi = T(0), axi = T(0);
+    if (act) {
+        node_coords(g, i, X, Y, Z);
+        dir = is_dirichlet(g, X, Y, Z);
+        sx[i] = x[i];
+        if (INV) sk[i] = kap[i];
+        bi = b[i];
+        if (MODE == M_FD_PLAIN) axi = Ax[i];
+    }
+    // this thread's element (if any): element i of the level
+    int ex = 0, ey = 0, ez = 0;
+    const bool has_el = i < ne;
+    if (has_el) {
+        ex = i % g.nx;
+        const int rest = i / g.nx;
+        ey = DIM == 3 ? rest % g.ny : rest;
+        ez = DIM == 3 ? rest / g.ny : 0;
+    }
+    __syncthreads();
+
+    // q_i = ((J - shift I) v)_i for the direction whose entry here is vi, vv = v.v
+    auto apply = [&](T vi, double vv, double shift) -> T {
+        const double eps = vv > 0.0 ? epsn / sqrt(vv) : 0.0;
+        const T e = (T)eps;
+        if (act) sv[i] = dir ? T(0) : vi;
+        __syncthreads();
+        if (has_el && eps != 0.0) {
+            T xe[1][NV], ve[1][NV], kp[NV], r8[1][NV];
+#pragma unroll
+            for (int a = 0; a < NV; ++a) {
+                const int j = (int)node_index(g, ex + (a & 1), ey + ((a >> 1) & 1), ez + ((a >> 2) & 1));
+                xe[0][a] = sx[j];
+                ve[0][a] = sv[j];
+                kp[a] = INV ? sk[j] : T(0);
+            }
+            elem_eval<DIM, KIND, MODE, T, 1, NV>(xe, ve, kp, e, ph, h, r8);
+#pragma unroll
+            for (int a = 0; a < NV; ++a) ew[a * ne + i] = r8[0][a];
+        }
+        __syncthreads();
+        T val = T(0);
+        if (act && !dir && eps != 0.0) {
+#pragma unroll
+            for (int a = 0; a < NV; ++a) {   // the element whose corner a is this node
+                const int cx = X - (a & 1), cy = Y - ((a >> 1) & 1), cz = DIM == 3 ? Z - ((a >> 2) & 1) : 0;
+                if (cx < 0 || cx >= g.nx || cy < 0 || cy >= g.ny) continue;
+                if (DIM == 3 && (cz < 0 || cz >= g.nz)) continue;
+                val += ew[a * ne + (cz * g.ny + cy) * g.nx + cx];
+            }
+            if constexpr (MODE == M_FD_PLAIN) val = (val - axi) * (T)(1.0 / eps);
+        }
+        return dir ? T(0) : val - (T)shift * vi;
+    };
+
+    const double bb = cg_bsum((double)bi * (double)bi);
+    const double tol = fmax(ca.atol, ca.rtol * sqrt(bb));
+    long long fd = 0, iters = 0;
+    bool s_nonzero = false;
+    T si = T(0), ri = T(0), pi = T(0), qi = T(0);
+
+    auto cg = [&](double shift) -> double {
+        if (s_nonzero) {
+            const double ss = cg_bsum((double)si * (double)si);
+            qi = apply(si, ss, shift);
+            ++fd;
+            ri = bi - qi;
+        } else {
+            ri = bi;
+        }
+        pi = ri;
+        double rr = cg_bsum((double)ri * (double)ri);
+        if (sqrt(rr) <= tol) return 0.0;
+        double pp = rr;
+        for (int it = 1; it <= ca.maxit; ++it) {
+            qi = apply(pi, pp, shift);
+            ++fd;
+            ++iters;
+            const double pq = cg_bsum((double)pi * (double)qi);
+            if (pq <= 0.0) return pq / pp;
+            const double alpha = rr / pq;
+            const T a = (T)alpha;
+            si += a * pi;
+            ri -= a * qi;
+            s_nonzero = true;
+            const double rn = cg_bsum((double)ri * (double)ri);
+            if (sqrt(rn) <= tol) return 0.0;
+            const T beta = (T)(rn / rr);
+            pi = ri + beta * pi;
+            pp = cg_bsum((double)pi * (double)pi);
+            rr = rn;
+        }
+        return 0.0;
+    };
+
+    double shift = 0.0;
+    double lam_c = cg(shift);
+    int rounds = 0;
+    int negc = lam_c < 0.0 ? 1 : 0;
+    while (lam_c < 0.0 && rounds < ca.shift_max) {
+        shift = ca.gamma * fmin(lam_c, shift);
+        lam_c = cg(shift);
+        if (lam_c < 0.0) ++negc;
+        ++rounds;
+    }
+    if (act) s_out[i] = si;
+    if (threadIdx.x == 0) {
+        ca.stats[0] = shift;
+        ca.stats[1] += (double)iters;
+        ca.stats[2] = rounds;
+        ca.stats[3] += (double)fd;
+        ca.stats[4] += (double)negc;
+        ca.stats[5] += 1.0;
+    }
+}
+
 template <int DIM, int KIND, typename T>
 static void launch_coarse(const Exec &ex, int mode, const Grid &g, const Phys &ph, const T *kap, const T *x,
                           const T *Ax, const double *num, const T *b, T *s, T *work, const CoarseArgs &ca) {
+    if constexpr (KIND != JFNK_NEOHOOKE) {
+        const long long ne = (long long)g.nx * g.ny * (DIM == 3 ? g.nz : 1);
+        const size_t lds = (size_t)((KIND == JFNK_INVCOEF ? 3 : 2) * g.nn + Cell<DIM>::NV * ne) * sizeof(T);
+        if (g.nn <= CBLOCK && lds <= 64 * 1024) {
+            if (mode == M_FD_DIFF)
+                k_coarse_small<DIM, KIND, M_FD_DIFF, T><<<1, CBLOCK, lds, ex.st>>>(g, ph, kap, x, Ax, num, b, s, ca);
+            else
+                k_coarse_small<DIM, KIND, M_FD_PLAIN, T><<<1, CBLOCK, lds, ex.st>>>(g, ph, kap, x, Ax, num, b, s, ca);
+            return;
+        }
+    }
     if (mode == M_FD_DIFF)
         k_coarse<DIM, KIND, M_FD_DIFF, T><<<1, CBLOCK, 0, ex.st>>>(g, ph, kap, x, Ax, num, b, s, work, ca);
     else

@@ -181,7 +181,8 @@ void plan(jfnk_ctx *c, Carve &cv) {
         L.t = cv.take(vb);
         L.eig = cv.take(vb);
         L.q = cv.take(vb);
-        L.cw = l == 0 ? cv.take(4 * vb) : nullptr;
+        // coarse solver: r, p, q and the per-element contributions (8 per element)
+        L.cw = l == 0 ? cv.take(11 * vb) : nullptr;
     }
     const Grid gf = level_grid(c->prob, c->prob.nlevels - 1);
     c->nn = gf.nn;
