@@ -309,11 +309,77 @@ __device__ __forceinline__ void elem_eval(const T (*xe)[NV], const T (*ve)[NV], 
 
 // ---- node-centric value ---------------------------------------------------------------
 // Sum of the contributions of the elements around node (X, Y, Z).
+// Scalar kinds: the 3^DIM neighbourhood of x, v (and e^m) is loaded into
+// registers first (clamped indices, all loads in flight together), then the
+// 2^DIM elements around the node are evaluated from registers.
+template <int DIM, int KIND, int MODE, typename T, typename TV>
+__device__ __forceinline__ void node_value_scalar(const Grid &g, const Phys &ph, const T *kap, const T *x,
+                                                  const TV *v, const T *Ax, double eps, int X, int Y, int Z,
+                                                  long long i, T *val) {
+    constexpr int NV = Cell<DIM>::NV;
+    constexpr int NZ3 = DIM == 3 ? 3 : 1;
+    constexpr int NB = 9 * NZ3;
+    constexpr bool FD = MODE != M_RESID;
+    constexpr bool INV = KIND == JFNK_INVCOEF;
+    val[0] = T(0);
+    if (FD && eps == 0.0) return;
+    const T h = (T)g.h;
+    const T e = (T)eps;
+    T nx[NB], nv[NB], nk[NB];
+    bool ok[3][3];     // [axis][offset]: neighbour index inside the grid
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ok[0][d] = X + d - 1 >= 0 && X + d - 1 < g.NX;
+        ok[1][d] = Y + d - 1 >= 0 && Y + d - 1 < g.NY;
+        ok[2][d] = DIM == 3 ? (Z + d - 1 >= 0 && Z + d - 1 < g.NZ) : d == 1;
+    }
+#pragma unroll
+    for (int dz = 0; dz < NZ3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int k = (dz * 3 + dy) * 3 + dx;
+                const int ax = min(max(X + dx - 1, 0), g.NX - 1), ay = min(max(Y + dy - 1, 0), g.NY - 1);
+                const int az = DIM == 3 ? min(max(Z + dz - 1, 0), g.NZ - 1) : 0;
+                const long long j = node_index(g, ax, ay, az);
+                const bool in = ok[0][dx] && ok[1][dy] && ok[2][DIM == 3 ? dz : 1];
+                nx[k] = x[j];
+                nv[k] = FD ? (T)v[j] : T(0);
+                nk[k] = INV ? kap[j] : T(0);
+                if (FD && (!in || is_dirichlet(g, ax, ay, az))) nv[k] = T(0);
+                if (!in) { nx[k] = T(0); nk[k] = T(0); }
+            }
+#pragma unroll
+    for (int el = 0; el < NV; ++el) {
+        const int ox = 1 - (el & 1), oy = 1 - ((el >> 1) & 1), oz = DIM == 3 ? 1 - ((el >> 2) & 1) : 0;
+        const bool inside = ok[0][ox] && ok[1][oy] && (DIM == 2 || ok[2][oz]) &&
+                            X - (el & 1) < g.nx && Y - ((el >> 1) & 1) < g.ny &&
+                            (DIM == 2 || Z - ((el >> 2) & 1) < g.nz);
+        if (!inside) continue;
+        T xe[1][NV], ve[1][NV], kp[NV], r[1][NV];
+#pragma unroll
+        for (int a = 0; a < NV; ++a) {
+            const int k = ((oz + ((a >> 2) & 1)) * 3 + oy + ((a >> 1) & 1)) * 3 + ox + (a & 1);
+            xe[0][a] = nx[k];
+            ve[0][a] = nv[k];
+            kp[a] = nk[k];
+        }
+        elem_eval<DIM, KIND, MODE, T, 1, NV>(xe, ve, kp, e, ph, h, r);
+        val[0] += r[0][el];
+    }
+    if constexpr (MODE == M_FD_PLAIN) val[0] = (val[0] - Ax[i]) * (T)(1.0 / eps);
+}
+
 template <int DIM, int KIND, int MODE, typename T, typename TV>
 __device__ __forceinline__ void node_value(const Grid &g, const Phys &ph, const T *kap, const T *x, const TV *v,
                                            const T *Ax, double eps, int X, int Y, int Z, long long i, T *val) {
     constexpr int NV = Cell<DIM>::NV;
     constexpr int NC = (KIND == JFNK_NEOHOOKE) ? 3 : 1;
+    if constexpr (NC == 1) {
+        node_value_scalar<DIM, KIND, MODE, T, TV>(g, ph, kap, x, v, Ax, eps, X, Y, Z, i, val);
+        return;
+    }
     const long long nn = g.nn;
 #pragma unroll
     for (int c = 0; c < NC; ++c) val[c] = T(0);
