@@ -52,6 +52,23 @@ __device__ __forceinline__ void stiff_apply(const T *u, T *Ku) {
     }
 }
 
+// KS (K u) with KS = 12 in 3D, where 12 K has integer entries (4 on the
+// diagonal, -1 between corners that differ in two or three coordinates, 0
+// between edge neighbours), so each entry is one multiply-add; KS = 1 in 2D.
+template <int DIM> struct KScale { static constexpr double value = DIM == 3 ? 12.0 : 1.0; };
+template <int DIM, typename T>
+__device__ __forceinline__ void stiff_apply_s(const T *u, T *Ku) {
+    if (DIM == 2) {
+        stiff_apply<2, T>(u, Ku);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const T far = (u[a ^ 3] + u[a ^ 5]) + (u[a ^ 6] + u[a ^ 7]);
+            Ku[a] = T(4) * u[a] - far;
+        }
+    }
+}
+
 // Square root and quotient: IEEE-rounded in FP64; in FP32 the hardware
 // approximations (about 1 ulp), which the FP32 multigrid levels tolerate.
 template <typename T> __device__ __forceinline__ T hw_sqrt(T x) { return sqrt(x); }
@@ -76,12 +93,16 @@ __device__ __forceinline__ T plap_pow(T base, double p, int which) {
 // ---------------------------------------------------------------------------
 // scalar kinds: r[a] for one element.  w: state corners, kap: e^{m} corners
 // ---------------------------------------------------------------------------
+// m multiplies the whole element vector (0 switches an element off without
+// a branch).
 template <int DIM, int KIND, typename T, int PF = 0>
-__device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys &ph, T h, T *r) {
+__device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys &ph, T h, T *r, T m = T(1)) {
     constexpr int NV = Cell<DIM>::NV;
+    constexpr double KS = KScale<DIM>::value;
     T Ku[NV];
-    stiff_apply<DIM, T>(w, Ku);
+    stiff_apply_s<DIM, T>(w, Ku);                 // KS K u
     const T hs = (DIM == 3) ? h : T(1);          // h^(d-2)
+    const T hk = hs * T(1.0 / KS) * m;
     if (KIND == JFNK_BRATU) {
         T vol = (DIM == 3) ? h * h * h : h * h;
         T wq = vol / T(NV);
@@ -97,17 +118,17 @@ __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys
 #pragma unroll
             for (int a = 0; a < NV; ++a) src[a] += e * phi_gauss<DIM, T>(__builtin_popcount(a ^ q));
         }
-        T lw = T(ph.a0) * wq;
+        T lw = T(ph.a0) * wq * m;
 #pragma unroll
-        for (int a = 0; a < NV; ++a) r[a] = hs * Ku[a] - lw * src[a];
+        for (int a = 0; a < NV; ++a) r[a] = hk * Ku[a] - lw * src[a];
     } else if (KIND == JFNK_PLAP) {
         T quad = T(0);
 #pragma unroll
         for (int a = 0; a < NV; ++a) quad += w[a] * Ku[a];
-        // s = u^T K_e u / |e| = quad * h^(d-2) / h^d = quad / h^2
-        T s = quad / (h * h);
+        // s = u^T K_e u / |e| = quad * h^(d-2) / h^d = quad / h^2  (quad carries KS)
+        T s = quad * (T(1) / (T(KS) * h * h));
         T d2 = T(ph.a1) * T(ph.a1);
-        T k = plap_pow<T, PF>(d2 + s, ph.a0, 0) * hs;
+        T k = plap_pow<T, PF>(d2 + s, ph.a0, 0) * hk;
 #pragma unroll
         for (int a = 0; a < NV; ++a) r[a] = k * Ku[a];
     } else {  // INVCOEF
@@ -115,7 +136,7 @@ __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys
 #pragma unroll
         for (int a = 0; a < NV; ++a) { ks += kap[a]; us += w[a]; }
         T kb = ks / T(NV), ub = us / T(NV);
-        T k = kb * (T(1) + ub * ub) * hs;
+        T k = kb * (T(1) + ub * ub) * hk;
 #pragma unroll
         for (int a = 0; a < NV; ++a) r[a] = k * Ku[a];
     }
@@ -160,11 +181,13 @@ __device__ __forceinline__ T elem_scalar_energy(const T *w, const Phys &ph, T h)
 // destroys the action on smooth directions).
 template <int DIM, int KIND, typename T, int PF = 0>
 __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *kap, T eps, const Phys &ph,
-                                               T h, T *q) {
+                                               T h, T *q, T m = T(1)) {
     constexpr int NV = Cell<DIM>::NV;
+    constexpr double KS = KScale<DIM>::value;
     const T hs = (DIM == 3) ? h : T(1);
+    const T hk = hs * T(1.0 / KS) * m;            // undoes KS; m switches the element off
     T Kv[NV];
-    stiff_apply<DIM, T>(v, Kv);
+    stiff_apply_s<DIM, T>(v, Kv);
     if (KIND == JFNK_BRATU) {
         // sum_q w_q (e^{w_q} - e^{x_q}) phi_a / eps = sum_q w_q e^{x_q} expm1(eps v_q) / eps phi_a
         T vol = (DIM == 3) ? h * h * h : h * h;
@@ -186,13 +209,13 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
 #pragma unroll
             for (int a = 0; a < NV; ++a) src[a] += e * phi_gauss<DIM, T>(__builtin_popcount(a ^ qq));
         }
-        const T lw = T(ph.a0) * wq;
+        const T lw = T(ph.a0) * wq * m;
 #pragma unroll
-        for (int a = 0; a < NV; ++a) q[a] = hs * Kv[a] - lw * src[a];
+        for (int a = 0; a < NV; ++a) q[a] = hk * Kv[a] - lw * src[a];
         return;
     }
     T Kx[NV];
-    stiff_apply<DIM, T>(x, Kx);
+    stiff_apply_s<DIM, T>(x, Kx);
     T kw, dk;
     if (KIND == JFNK_PLAP) {
         T qxx = T(0), qxv = T(0), qvv = T(0);
@@ -202,7 +225,7 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
             qxv += x[a] * Kv[a];
             qvv += v[a] * Kv[a];
         }
-        const T ih2 = T(1) / (h * h);
+        const T ih2 = T(1) / (T(KS) * h * h);
         const T bx = T(ph.a1) * T(ph.a1) + qxx * ih2;
         const T dsq = (T(2) * qxv + eps * qvv) * ih2;        // (s_w - s_x) / eps
         const T bw = bx + eps * dsq;
@@ -230,8 +253,9 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
         kw = kb * (T(1) + wb * wb);
         dk = kb * vb * (T(2) * xb + eps * vb);
     }
+    const T cv = hk * kw, cx = hk * dk;
 #pragma unroll
-    for (int a = 0; a < NV; ++a) q[a] = hs * (kw * Kv[a] + dk * Kx[a]);
+    for (int a = 0; a < NV; ++a) q[a] = cv * Kv[a] + cx * Kx[a];
 }
 
 // Exact J_e^T lam (= J_e lam for the symmetric kinds), FP64 use.

@@ -277,9 +277,10 @@ template <typename T, int NC> struct EpiPower {
 
 // ---- one element in any mode ------------------------------------------------------
 // xe: state corners; ve: direction corners (FD modes); r: output contributions
+// m (scalar kinds): multiplies the element vector; 0 switches the element off
 template <int DIM, int KIND, int MODE, typename T, int NC, int NV, int PF = 0>
 __device__ __forceinline__ void elem_eval(const T (*xe)[NV], const T (*ve)[NV], const T *kp, T eps,
-                                          const Phys &ph, T h, T (*r)[NV]) {
+                                          const Phys &ph, T h, T (*r)[NV], T m = T(1)) {
     if constexpr (KIND == JFNK_NEOHOOKE) {
         if constexpr (MODE == M_FD_DIFF) {
             elem_neohooke_fd<T>(xe, ve, eps, ph, h, r);
@@ -295,14 +296,14 @@ __device__ __forceinline__ void elem_eval(const T (*xe)[NV], const T (*ve)[NV], 
         }
     } else {
         if constexpr (MODE == M_FD_DIFF) {
-            elem_scalar_fd<DIM, KIND, T, PF>(xe[0], ve[0], kp, eps, ph, h, r[0]);
+            elem_scalar_fd<DIM, KIND, T, PF>(xe[0], ve[0], kp, eps, ph, h, r[0], m);
         } else if constexpr (MODE == M_FD_PLAIN) {
             T w[NV];
 #pragma unroll
             for (int a = 0; a < NV; ++a) w[a] = xe[0][a] + eps * ve[0][a];
-            elem_scalar<DIM, KIND, T, PF>(w, kp, ph, h, r[0]);
+            elem_scalar<DIM, KIND, T, PF>(w, kp, ph, h, r[0], m);
         } else {
-            elem_scalar<DIM, KIND, T, PF>(xe[0], kp, ph, h, r[0]);
+            elem_scalar<DIM, KIND, T, PF>(xe[0], kp, ph, h, r[0], m);
         }
     }
 }

@@ -25,13 +25,13 @@
 
 namespace jfnk {
 
-// node rows per tile (register arrays).  FP32: 4, which keeps the kernel
-// under 128 VGPRs (4 waves per SIMD); measured faster than 3, 5, 6 or 8 at
-// 256^3 despite the larger y halo.  FP64: 8 for the residual and the plain
-// FD quotient without epilogue inputs, 4 for the others (register budget).
+// node rows per tile (register arrays), chosen by measurement at 256^3:
+// FP32 4 (under 128 VGPRs, 4 waves per SIMD; faster than 3, 5, 6 or 8
+// despite the larger y halo); FP64 6 for the plain FD quotient without
+// epilogue inputs (the outer J v; 8 spills registers), 4 otherwise.
 template <typename T, int MODE, class Epi> struct TileRows {
-    static constexpr bool wide = MODE == M_RESID || (MODE == M_FD_PLAIN && Epi::NIN == 0);
-    static constexpr int value = (sizeof(T) == 8 && wide) ? 8 : 4;
+    static constexpr bool jv64 = sizeof(T) == 8 && MODE == M_FD_PLAIN && Epi::NIN == 0;
+    static constexpr int value = jv64 ? 6 : 4;
 };
 constexpr int TMAX_THREADS = 512;   // nx <= 512 elements per row
 
@@ -188,27 +188,29 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         for (int re = 0; re <= R; ++re) {
             if (re > rows) break;
             T r8[1][8];
-#pragma unroll
-            for (int a = 0; a < 8; ++a) r8[0][a] = T(0);
             if (lz) {
                 T ux[4], uk[4];
                 TV uv[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { uk[c] = T(0); uv[c] = TV(0); }
                 row(re + 1, ux, uv, uk);
+                // element rows outside the grid read zero-filled halo rows and are
+                // switched off by the factor m (no branch)
                 const int ey = y0 - 1 + re;
-                if (ey >= 0 && ey < g.ny) {
-                    // corner a = ax + 2 ay + 4 az
-                    const T xe[1][8] = {{cx[0], cx[1], ux[0], ux[1], cx[2], cx[3], ux[2], ux[3]}};
-                    T ve[1][8], kp[8];
-                    const TV vv[8] = {cv[0], cv[1], uv[0], uv[1], cv[2], cv[3], uv[2], uv[3]};
-                    const T kk[8] = {ck[0], ck[1], uk[0], uk[1], ck[2], ck[3], uk[2], uk[3]};
+                const T m = (ey >= 0 && ey < g.ny) ? T(1) : T(0);
+                // corner a = ax + 2 ay + 4 az
+                const T xe[1][8] = {{cx[0], cx[1], ux[0], ux[1], cx[2], cx[3], ux[2], ux[3]}};
+                T ve[1][8], kp[8];
+                const TV vv[8] = {cv[0], cv[1], uv[0], uv[1], cv[2], cv[3], uv[2], uv[3]};
+                const T kk[8] = {ck[0], ck[1], uk[0], uk[1], ck[2], ck[3], uk[2], uk[3]};
 #pragma unroll
-                    for (int a = 0; a < 8; ++a) { ve[0][a] = (T)vv[a]; kp[a] = kk[a]; }
-                    elem_eval<3, KIND, MODE, T, 1, 8, PF>(xe, ve, kp, e, ph, h, r8);
-                }
+                for (int a = 0; a < 8; ++a) { ve[0][a] = (T)vv[a]; kp[a] = kk[a]; }
+                elem_eval<3, KIND, MODE, T, 1, 8, PF>(xe, ve, kp, e, ph, h, r8, m);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { cx[c] = ux[c]; cv[c] = uv[c]; ck[c] = uk[c]; }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 8; ++a) r8[0][a] = T(0);
             }
             if (re >= 1) {     // node row re - 1 is complete for this layer
                 const int k = re - 1;
