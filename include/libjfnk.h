@@ -298,7 +298,7 @@ jfnk_status jfnk_assemble_load(jfnk_ctx *ctx, int kind, const double *params, in
 /* ---- measurement ----------------------------------------------------------- */
 /* Kernel classes that can be timed with stream events around each launch. */
 typedef enum {
-    JFNK_TIMER_CHEB_FINE = 0,   /* fused Chebyshev step on the finest level */
+    JFNK_TIMER_CHEB_FINE = 0,   /* interior fused Chebyshev steps on the finest level */
     JFNK_TIMER_JV_OUTER = 1,    /* FP64 outer FD Jacobian action */
     JFNK_TIMER_RESID_FINE = 2,  /* FP64 finest-level residual */
     JFNK_TIMER_ARNOLDI = 3,     /* Gram-Schmidt passes of FGMRES */

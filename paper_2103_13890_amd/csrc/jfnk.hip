@@ -438,7 +438,6 @@ void chebyshev(jfnk_ctx *c, int l, const T *b, T *s, int nu, bool zero, T *out, 
             b_n2 = lslot(c, l, L_B);
         }
         const double rn = 1.0 / (2.0 * k.sigma - rho);
-        TimeScope ts(c, fine ? JFNK_TIMER_CHEB_FINE : JFNK_TIMER_COUNT);
         op_cheb_first<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), b, lslot(c, l, L_NUM),
                          b_n2, P<T>(L.r), s, P<T>(L.d[1]), 1.0 / k.theta, rn * rho, 2.0 * rn / k.delta,
                          lslot(c, l, L_D1));
@@ -456,16 +455,19 @@ void chebyshev(jfnk_ctx *c, int l, const T *b, T *s, int nu, bool zero, T *out, 
     for (int it = first_it; it < nu - 1; ++it) {
         const double rn = 1.0 / (2.0 * k.sigma - rho);
         const double c1 = rn * rho, c2 = 2.0 * rn / k.delta;
-        TimeScope ts(c, fine ? JFNK_TIMER_CHEB_FINE : JFNK_TIMER_COUNT);
         if (it == nu - 2) {
             op_cheb_last<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), CP<T>(L.d[cur]),
                             lslot(c, l, L_NUM), lslot(c, l, cur ? L_D1 : L_D0), CP<T>(L.r), s, out, c1, c2, out_n2);
             c->ge[l] += 1;
             return;
         }
-        op_cheb_step<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), CP<T>(L.d[cur]),
-                        lslot(c, l, L_NUM), lslot(c, l, cur ? L_D1 : L_D0), P<T>(L.r), s, P<T>(L.d[1 - cur]), c1,
-                        c2, lslot(c, l, cur ? L_D0 : L_D1));
+        {
+            // the timer brackets the interior steps only (28 B/node each)
+            TimeScope ts(c, fine ? JFNK_TIMER_CHEB_FINE : JFNK_TIMER_COUNT);
+            op_cheb_step<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), CP<T>(L.d[cur]),
+                            lslot(c, l, L_NUM), lslot(c, l, cur ? L_D1 : L_D0), P<T>(L.r), s, P<T>(L.d[1 - cur]),
+                            c1, c2, lslot(c, l, cur ? L_D0 : L_D1));
+        }
         c->ge[l] += 1;
         rho = rn;
         cur = 1 - cur;

@@ -249,12 +249,15 @@ def test_smoother(kind, form):
         gl = lev.grid
         bl = W.normal_vector(gl.n, w['faces'], 141 + l, ncomp=ncomp(w))
         s0 = W.normal_vector(gl.n, w['faces'], 151 + l, ncomp=ncomp(w))
-        for zero in (True, False):
-            s = to_dev(s0)
-            api.mg_smooth(ctx, l, to_dev(bl), s, 3, zero)
-            ref = OM.chebyshev(lambda x: OM.level_jv(pb, lev, x), bl, 0 * s0 if zero else s0, 3, lev.lam,
-                               opts.cheb_lo, opts.cheb_hi, s_is_zero=zero)
-            assert rel(to_np(s), ref) < 1e-10
+        # every degree path: nu = 1 (no J v), 2 (start and last step), 3 and
+        # more (fused first step from s = 0, plain steps, fused last step)
+        for nu in (1, 2, 3, 5):
+            for zero in (True, False):
+                s = to_dev(s0)
+                api.mg_smooth(ctx, l, to_dev(bl), s, nu, zero)
+                ref = OM.chebyshev(lambda x: OM.level_jv(pb, lev, x), bl, 0 * s0 if zero else s0, nu, lev.lam,
+                                   opts.cheb_lo, opts.cheb_hi, s_is_zero=zero)
+                assert rel(to_np(s), ref) < 1e-10, (l, nu, zero)
 
 
 def test_coarse_solve_spd_and_shift():
