@@ -55,6 +55,8 @@ struct jfnk_ctx {
     hipStream_t st = nullptr;
     Exec ex;
     double *scal = nullptr, *part = nullptr;
+    double *lazy_part = nullptr;   // partial buffers of the deferred slots
+    LazyTable lazy;
     // finest level, FP64
     long long nn = 0, n = 0;
     double *u = nullptr, *ut = nullptr, *Au = nullptr, *Aut = nullptr, *F = nullptr, *Ft = nullptr;
@@ -166,6 +168,7 @@ void plan(jfnk_ctx *c, Carve &cv) {
     const size_t es = esize(c->vprec);
     c->scal = (double *)cv.take(NSLOT * sizeof(double));
     c->part = (double *)cv.take(PART_CAP * sizeof(double));
+    c->lazy_part = (double *)cv.take((size_t)(4 * c->prob.nlevels + 1) * LAZY_CAP * sizeof(double));
     for (int l = 0; l < c->prob.nlevels; ++l) {
         Level &L = c->lev[l];
         L.g = level_grid(c->prob, l);
@@ -224,6 +227,7 @@ double *slot(jfnk_ctx *c, int i) { return c->scal + i; }
 double *lslot(jfnk_ctx *c, int l, int k) { return c->scal + S_LEV + 16 * l + k; }
 
 jfnk_status read_slots(jfnk_ctx *c, int first, int count, double *out) {
+    for (int i = first; i < first + count; ++i) materialize(c->ex, c->scal + i);
     HIPCHK(c, hipMemcpyAsync(out, c->scal + first, count * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     return JFNK_OK;
@@ -887,6 +891,17 @@ jfnk_status jfnk_create(const jfnk_problem *p, const jfnk_options *o, void *ws, 
     c->ex.st = c->st;
     c->ex.red.part = c->part;
     c->ex.path = o->kernel_path;
+    // deferred reductions: the norms that only the next FD evaluation reads
+    // (Chebyshev directions, smoothed corrections, restricted loads, the
+    // preconditioned direction of the outer Krylov step)
+    {
+        int k = 0;
+        auto reg = [&](double *sl) { c->lazy.buf[sl] = c->lazy_part + (size_t)(k++) * LAZY_CAP; };
+        for (int l = 0; l < p->nlevels; ++l)
+            for (int w : {L_D0, L_D1, L_S, L_B}) reg(lslot(c, l, w));
+        reg(slot(c, S_ZN2));
+        c->ex.lazy = &c->lazy;
+    }
     for (int l = 0; l < JFNK_MAX_LEVELS; ++l) c->ge[l] = 0.0;
     hipError_t e = hipMemsetAsync(c->scal, 0, NSLOT * sizeof(double), c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);

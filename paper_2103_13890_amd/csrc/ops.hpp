@@ -6,12 +6,11 @@
 
 namespace jfnk {
 
-struct FdStep;
-
 struct Exec {
     hipStream_t st;
     Red red;
     int path;            // 0 auto, 1 node-centric, 2 z-marching tiles
+    LazyTable *lazy = nullptr;   // deferred reductions (nullable)
     // when set, recorded on st right after the next stencil kernel (before
     // its reduction finish) and cleared: lets a timer bracket that kernel
     mutable hipEvent_t ev_main_end = nullptr;
@@ -22,6 +21,50 @@ struct Exec {
         }
     }
 };
+
+// ---- reductions into slots ------------------------------------------------------
+// Partial-sum buffer for a reduction of nb blocks whose result goes to slot:
+// the slot's own buffer when the slot is deferred, else the shared one.
+inline Red red_for(const Exec &ex, const double *slot, int nb) {
+    if (ex.lazy && slot && nb <= LAZY_CAP) {
+        auto it = ex.lazy->buf.find(slot);
+        if (it != ex.lazy->buf.end()) return Red{it->second};
+    }
+    return ex.red;
+}
+// After the producer: record the partials of a deferred slot, or run the
+// finishing kernel (which writes the slot).
+template <int NS, class Fin>
+inline void finish_to(const Exec &ex, const double *slot, const Red &r, int nb, const Fin &fin) {
+    if (ex.lazy && slot) {
+        if (NS == 1 && r.part != ex.red.part) {
+            ex.lazy->pend[slot] = Pending{r.part, nb};
+            return;
+        }
+        ex.lazy->pend.erase(slot);
+    }
+    finish<NS>(ex.st, r, nb, fin);
+}
+// Write a deferred slot's value (for a consumer that reads the slot itself).
+inline void materialize(const Exec &ex, double *slot) {
+    if (!ex.lazy || !slot) return;
+    auto it = ex.lazy->pend.find(slot);
+    if (it == ex.lazy->pend.end()) return;
+    finish<1>(ex.st, Red{const_cast<double *>(it->second.part)}, it->second.nb, FinStore<1>{slot});
+    ex.lazy->pend.erase(it);
+}
+// FD step descriptor: a deferred ||v||^2 is summed by the consuming kernel.
+inline FdStep make_fd(const Exec &ex, const double *num, const double *vn2, double fixed) {
+    FdStep f{num, vn2, fixed};
+    if (ex.lazy && vn2 && !(fixed > 0.0)) {
+        auto it = ex.lazy->pend.find(vn2);
+        if (it != ex.lazy->pend.end()) {
+            f.part = it->second.part;
+            f.nb = it->second.nb;
+        }
+    }
+    return f;
+}
 
 // a1 residual: F = A(u) - b (b nullable), A(u) -> Aout (nullable), ||F||^2 -> nrm2 (nullable)
 template <typename T>

@@ -10,7 +10,7 @@ template <>
 void op_jv<double, float>(const Exec &ex, int mode, const Grid &g, const Phys &ph, const double *kap,
                           const double *x, const double *Ax, const float *v, const double *num, const double *vn2,
                           double eps_fixed, double *Jv) {
-    dispatch_fd<double, float, EpiJv>(ex, mode, g, ph, kap, x, v, Ax, FdStep{num, vn2, eps_fixed}, Jv, g.nn);
+    dispatch_fd<double, float, EpiJv>(ex, mode, g, ph, kap, x, v, Ax, make_fd(ex, num, vn2, eps_fixed), Jv, g.nn);
 }
 
 // ---- energy: sum over elements of Psi_e(u) ----------------------------------

@@ -4,6 +4,8 @@
 // floating-point atomics, so every result is bitwise reproducible for a
 // given launch shape.
 #pragma once
+#include <map>
+
 #include "common.hpp"
 
 namespace jfnk {
@@ -73,6 +75,49 @@ __global__ __launch_bounds__(256) void k_finish(Red red, int nb, Fin fin) {
     block_sum<NS>(acc, scratch, tot);
     if (threadIdx.x == 0) fin(tot);
 }
+
+// Step of the finite-difference quotient (Sec. 1): eps = num / ||v||, read
+// from device slots at kernel start, or a fixed test step.  ||v||^2 is either
+// a slot or, for a deferred reduction, the per-block partials of the kernel
+// that produced v: then every block sums them itself, in the same order as
+// k_finish does with a 256-thread block.
+struct FdStep {
+    const double *num;             // numerator slot (nullptr: not an FD evaluation)
+    const double *vn2;             // ||v||^2 slot
+    double fixed;                  // > 0: use this step
+    const double *part = nullptr;  // deferred ||v||^2: partials of nb blocks
+    int nb = 0;
+    // called by every thread of the block (a block-wide sum when deferred)
+    __device__ double eps() const {
+        if (fixed > 0.0) return fixed;
+        if (num == nullptr) return 0.0;
+        double n2;
+        if (part) {
+            __shared__ double scratch[MAX_WAVES];
+            __shared__ double tot[1];
+            double a[1] = {0.0};
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) a[0] += part[b];
+            block_sum<1>(a, scratch, tot);
+            n2 = tot[0];
+        } else {
+            n2 = *vn2;
+        }
+        return n2 > 0.0 ? *num / sqrt(n2) : 0.0;
+    }
+};
+
+// Deferred reductions (host side).  A slot registered in buf gets the
+// per-block partials of its producer in a buffer of its own and no
+// finishing kernel; pend records them until the slot is produced again.
+constexpr int LAZY_CAP = 8192;     // partials per deferred slot
+struct Pending {
+    const double *part;
+    int nb;
+};
+struct LazyTable {
+    std::map<const double *, double *> buf;
+    std::map<const double *, Pending> pend;
+};
 
 // Finalisers: write the totals (or derived scalars) to device slots.
 struct FinNone {

@@ -24,18 +24,6 @@
 
 namespace jfnk {
 
-struct FdStep {
-    const double *num;   // numerator slot (nullptr: not an FD evaluation)
-    const double *vn2;   // ||v||^2 slot
-    double fixed;        // > 0: use this step
-    __device__ __forceinline__ double eps() const {
-        if (fixed > 0.0) return fixed;
-        if (num == nullptr) return 0.0;
-        double n2 = *vn2;
-        return n2 > 0.0 ? *num / sqrt(n2) : 0.0;
-    }
-};
-
 // ---- epilogues ---------------------------------------------------------------
 // NS: number of grid sums; NCOMP: components; NIN: values read per node and
 // component.  load(i, in) reads them (issued ahead of the element work by
@@ -66,6 +54,7 @@ template <typename T, int NC> struct EpiResidual {
         }
     }
     __device__ void operator()(const double *t) const { if (out) out[0] = t[0]; }
+    double *slot() const { return out; }
 };
 
 // J v
@@ -81,6 +70,7 @@ template <typename T, int NC> struct EpiJv {
         for (int c = 0; c < NC; ++c) Jv[c * nn + i] = dir ? T(0) : val[c];
     }
     __device__ void operator()(const double *) const {}
+    double *slot() const { return nullptr; }
 };
 
 // Chebyshev step k (three-term recurrence), q = J d_k:
@@ -121,6 +111,7 @@ template <typename T, int NC> struct EpiCheb {
         }
     }
     __device__ void operator()(const double *t) const { out[0] = t[0]; }
+    double *slot() const { return out; }
 };
 
 // First Chebyshev step from s = 0, with the direction b instead of
@@ -159,6 +150,7 @@ template <typename T, int NC> struct EpiChebFirst {
         }
     }
     __device__ void operator()(const double *t) const { out[0] = t[0]; }
+    double *slot() const { return out; }
 };
 
 // Last Chebyshev step k, q = J d_k: r' = r - q, d_{k+1} = c1 d_k + c2 r',
@@ -199,6 +191,7 @@ template <typename T, int NC> struct EpiChebLast {
         }
     }
     __device__ void operator()(const double *t) const { if (out) out[0] = t[0]; }
+    double *slot() const { return out; }
 };
 
 // t = b - J s  (the residual restricted in Algorithm 1)
@@ -218,6 +211,7 @@ template <typename T, int NC> struct EpiResidJv {
         for (int c = 0; c < NC; ++c) t[c * nn + i] = dir ? T(0) : in[c] - val[c];
     }
     __device__ void operator()(const double *) const {}
+    double *slot() const { return nullptr; }
 };
 
 // Chebyshev start from s != 0: r = b - J s, d = r / theta; ||d||^2 -> out
@@ -247,6 +241,7 @@ template <typename T, int NC> struct EpiChebInit {
         }
     }
     __device__ void operator()(const double *t) const { out[0] = t[0]; }
+    double *slot() const { return out; }
 };
 
 // power step: q = J v; v.q and ||q||^2 -> out[0..1]
@@ -273,6 +268,7 @@ template <typename T, int NC> struct EpiPower {
         }
     }
     __device__ void operator()(const double *t) const { out[0] = t[0]; out[1] = t[1]; }
+    double *slot() const { return out; }
 };
 
 // ---- one element in any mode ------------------------------------------------------

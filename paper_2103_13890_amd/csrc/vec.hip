@@ -55,8 +55,9 @@ __global__ void k_scale(Grid g, int nc, const TI *x, TO *y, double scale, const 
 template <typename TI, typename TO>
 void vec_cast(const Exec &ex, const Grid &g, int nc, const TI *x, TO *y, double *nrm2) {
     const int nb = vblocks(g.nn);
-    k_scale<TI, TO><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, y, 1.0, nullptr, ex.red, nrm2);
-    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
+    const Red r = red_for(ex, nrm2, nb);
+    k_scale<TI, TO><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, y, 1.0, nullptr, r, nrm2);
+    if (nrm2) finish_to<1>(ex, nrm2, r, nb, FinStore<1>{nrm2});
 }
 template void vec_cast<double, double>(const Exec &, const Grid &, int, const double *, double *, double *);
 template void vec_cast<double, float>(const Exec &, const Grid &, int, const double *, float *, double *);
@@ -67,8 +68,10 @@ template <typename T>
 void vec_scale(const Exec &ex, const Grid &g, int nc, const T *x, T *y, double scale, const double *rs,
                double *nrm2) {
     const int nb = vblocks(g.nn);
-    k_scale<T, T><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, y, scale, rs, ex.red, nrm2);
-    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
+    materialize(ex, const_cast<double *>(rs));
+    const Red r = red_for(ex, nrm2, nb);
+    k_scale<T, T><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, y, scale, rs, r, nrm2);
+    if (nrm2) finish_to<1>(ex, nrm2, r, nb, FinStore<1>{nrm2});
 }
 template void vec_scale<float>(const Exec &, const Grid &, int, const float *, float *, double, const double *, double *);
 template void vec_scale<double>(const Exec &, const Grid &, int, const double *, double *, double, const double *, double *);
@@ -141,8 +144,9 @@ template <typename T>
 void vec_cheb_zero(const Exec &ex, const Grid &g, int nc, const T *b, T *r, T *d, T *s, double inv_theta,
                    double *d_nrm2) {
     const int nb = vblocks(g.nn);
-    k_cheb_zero<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, b, r, d, s, (T)inv_theta, ex.red, d_nrm2);
-    finish<1>(ex.st, ex.red, nb, FinStore<1>{d_nrm2});
+    const Red rr = red_for(ex, d_nrm2, nb);
+    k_cheb_zero<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, b, r, d, s, (T)inv_theta, rr, d_nrm2);
+    finish_to<1>(ex, d_nrm2, rr, nb, FinStore<1>{d_nrm2});
 }
 template void vec_cheb_zero<float>(const Exec &, const Grid &, int, const float *, float *, float *, float *, double, double *);
 template void vec_cheb_zero<double>(const Exec &, const Grid &, int, const double *, double *, double *, double *, double, double *);
@@ -164,8 +168,9 @@ __global__ void k_add(Grid g, int nc, const T *s, const T *d, T *o, Red red, dou
 template <typename T>
 void vec_add(const Exec &ex, const Grid &g, int nc, const T *s, const T *d, T *o, double *nrm2) {
     const int nb = vblocks(g.nn);
-    k_add<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, s, d, o, ex.red, nrm2);
-    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
+    const Red r = red_for(ex, nrm2, nb);
+    k_add<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, s, d, o, r, nrm2);
+    if (nrm2) finish_to<1>(ex, nrm2, r, nb, FinStore<1>{nrm2});
 }
 template void vec_add<float>(const Exec &, const Grid &, int, const float *, const float *, float *, double *);
 template void vec_add<double>(const Exec &, const Grid &, int, const double *, const double *, double *, double *);
@@ -198,8 +203,9 @@ template <typename T>
 void vec_random(const Exec &ex, const Grid &g, int nc, unsigned long long seed, int level, T *v, double *nrm2) {
     unsigned long long s0 = seed + ((unsigned long long)level << 32);
     const int nb = vblocks(g.nn);
-    k_random<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, s0, v, ex.red, nrm2);
-    finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
+    const Red r = red_for(ex, nrm2, nb);
+    k_random<T><<<nb, BLOCK, 0, ex.st>>>(g, nc, s0, v, r, nrm2);
+    finish_to<1>(ex, nrm2, r, nb, FinStore<1>{nrm2});
 }
 template void vec_random<float>(const Exec &, const Grid &, int, unsigned long long, int, float *, double *);
 template void vec_random<double>(const Exec &, const Grid &, int, unsigned long long, int, double *, double *);
@@ -222,8 +228,9 @@ __global__ void k_dot(long long n, const TA *x, const TB *y, Red red, double *ou
 template <typename TA, typename TB>
 void vec_dot(const Exec &ex, long long n, const TA *x, const TB *y, double *out) {
     const int nb = vblocks(n);
-    k_dot<TA, TB><<<nb, BLOCK, 0, ex.st>>>(n, x, y, ex.red, out);
-    finish<1>(ex.st, ex.red, nb, FinStore<1>{out});
+    const Red r = red_for(ex, out, nb);
+    k_dot<TA, TB><<<nb, BLOCK, 0, ex.st>>>(n, x, y, r, out);
+    finish_to<1>(ex, out, r, nb, FinStore<1>{out});
 }
 template void vec_dot<double, double>(const Exec &, long long, const double *, const double *, double *);
 template void vec_dot<float, float>(const Exec &, long long, const float *, const float *, double *);
@@ -537,9 +544,10 @@ __global__ __launch_bounds__(BLOCK) void k_restrict3(Grid gf, Grid gc, const T *
 template <typename T>
 void tr_restrict(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *rf, T *rc, double *nrm2) {
     const int nb = vblocks(gc.nn);
-    if (gf.dim == 3 && nc == 1) k_restrict3<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, rf, rc, ex.red, nrm2);
-    else k_restrict<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, rf, rc, ex.red, nrm2);
-    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
+    const Red r = red_for(ex, nrm2, nb);
+    if (gf.dim == 3 && nc == 1) k_restrict3<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, rf, rc, r, nrm2);
+    else k_restrict<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, rf, rc, r, nrm2);
+    if (nrm2) finish_to<1>(ex, nrm2, r, nb, FinStore<1>{nrm2});
 }
 template void tr_restrict<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
 template void tr_restrict<double>(const Exec &, const Grid &, const Grid &, int, const double *, double *, double *);
@@ -616,9 +624,10 @@ __global__ __launch_bounds__(BLOCK) void k_prolong_add3(Grid gf, Grid gc, const 
 template <typename T>
 void tr_prolong_add(const Exec &ex, const Grid &gf, const Grid &gc, int nc, const T *cc, T *sf, double *nrm2) {
     const int nb = vblocks(gf.nn);
-    if (gf.dim == 3 && nc == 1) k_prolong_add3<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, cc, sf, ex.red, nrm2);
-    else k_prolong_add<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, cc, sf, ex.red, nrm2);
-    if (nrm2) finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
+    const Red r = red_for(ex, nrm2, nb);
+    if (gf.dim == 3 && nc == 1) k_prolong_add3<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, cc, sf, r, nrm2);
+    else k_prolong_add<T><<<nb, BLOCK, 0, ex.st>>>(gf, gc, nc, cc, sf, r, nrm2);
+    if (nrm2) finish_to<1>(ex, nrm2, r, nb, FinStore<1>{nrm2});
 }
 template void tr_prolong_add<float>(const Exec &, const Grid &, const Grid &, int, const float *, float *, double *);
 template void tr_prolong_add<double>(const Exec &, const Grid &, const Grid &, int, const double *, double *, double *);
