@@ -79,8 +79,7 @@ __global__ __launch_bounds__(256) void k_finish(Red red, int nb, Fin fin) {
 // Step of the finite-difference quotient (Sec. 1): eps = num / ||v||, read
 // from device slots at kernel start, or a fixed test step.  ||v||^2 is either
 // a slot or, for a deferred reduction, the per-block partials of the kernel
-// that produced v: then every block sums them itself, in the same order as
-// k_finish does with a 256-thread block.
+// that produced v: then every block sums them itself in a fixed order.
 struct FdStep {
     const double *num;             // numerator slot (nullptr: not an FD evaluation)
     const double *vn2;             // ||v||^2 slot
@@ -95,8 +94,16 @@ struct FdStep {
         if (part) {
             __shared__ double scratch[MAX_WAVES];
             __shared__ double tot[1];
-            double a[1] = {0.0};
-            for (int b = threadIdx.x; b < nb; b += blockDim.x) a[0] += part[b];
+            // eight independent loads in flight per trip
+            const int bd = blockDim.x;
+            double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int b = threadIdx.x;
+            for (; b + 7 * bd < nb; b += 8 * bd) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc[k] += part[b + k * bd];
+            }
+            for (; b < nb; b += bd) acc[0] += part[b];
+            double a[1] = {((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]))};
             block_sum<1>(a, scratch, tot);
             n2 = tot[0];
         } else {
