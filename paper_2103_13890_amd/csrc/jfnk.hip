@@ -1190,7 +1190,8 @@ jfnk_status jfnk_solve_steps(jfnk_ctx *c, double *u, const double *coef, const d
     jfnk_status last = JFNK_OK;
     while (t < 1.0 - 1e-12) {
         const double step = std::min(dt, 1.0 - t);
-        last = solve_once(c, u, coef, b, t + step, &one, false);
+        const double target = t + step >= 1.0 - 1e-12 ? 1.0 : t + step;   // the full load exactly
+        last = solve_once(c, u, coef, b, target, &one, false);
         if (last == JFNK_E_DEVICE || last == JFNK_E_INVAL) return last;
         if (first) rep->fnorm0 = one.fnorm0;
         first = false;
@@ -1209,13 +1210,13 @@ jfnk_status jfnk_solve_steps(jfnk_ctx *c, double *u, const double *coef, const d
         rep->fnorm = one.fnorm;
         if (rep->nhist < JFNK_MAX_HIST) {          // one history entry per attempted increment
             rep->fnorm_hist[rep->nhist] = one.fnorm;
-            rep->alpha_hist[rep->nhist] = t + step;
+            rep->alpha_hist[rep->nhist] = target;
             rep->eta_hist[rep->nhist] = step;
             rep->lin_hist[rep->nhist] = one.linear_iters;
             rep->nhist++;
         }
         if (last == JFNK_OK) {
-            t += step;
+            t = target;
         } else {
             dt = 0.5 * step;
             if (dt < 1e-6) break;
