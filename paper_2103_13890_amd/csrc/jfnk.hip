@@ -27,9 +27,12 @@ enum {
     S_COARSE = 16,          // 8 coarse statistics
     S_H1 = 32,              // 32
     S_H2 = 64,              // 32
+    S_SIG = 96,             // 32: inverse norms of the stored Krylov basis columns
     S_LEV = 128,            // 16 per level
 };
-enum { L_NUM = 0, L_D0, L_D1, L_S, L_B, L_PQ, L_PQ2, L_V, L_T };
+// per-level slots; L_PQ, L_PQB, L_PQC: rotating (Rayleigh quotient, ||q||^2)
+// pairs of the power iterations in flight
+enum { L_NUM = 0, L_D0, L_D1, L_S, L_B, L_PQ, L_PQ2, L_V, L_T, L_PQB, L_PQB2, L_PQC, L_PQC2 };
 
 struct Level {
     Grid g;
@@ -68,6 +71,9 @@ struct jfnk_ctx {
     std::string err;
     TimerRec timers[JFNK_TIMER_COUNT];
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    // pinned host copies of the power method's slot pairs, one event each
+    double *hpin = nullptr;
+    hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -296,35 +302,66 @@ double root_eps(jfnk_ctx *c, int prec, int mode = M_FD_PLAIN) {
 // ---------------------------------------------------------------------------
 // multigrid setup (Sec. 2): projection, level caches, power method
 // ---------------------------------------------------------------------------
+// Iterations of the power method queued before the host has tested the
+// previous ones.  On small levels an iteration takes less GPU time than the
+// host's round trip, which is then hidden; an iteration queued past the
+// stopping point is discarded and changes no result.  On large levels one
+// extra evaluation costs more than the round trip saves.
+inline int power_lookahead(long long n) { return n >= (1LL << 23) ? 0 : (n >= (1LL << 20) ? 1 : 2); }
+
 template <typename T> jfnk_status power_method(jfnk_ctx *c, int l) {
     Level &L = c->lev[l];
     const Grid &g = L.g;
     const int nc = c->nc;
-    T *v = P<T>(L.eig), *q = P<T>(L.q);
-    if (!c->have_eigs) vec_random<T>(c->ex, g, nc, c->opt.seed, l, v, lslot(c, l, L_V));
-    else vec_dot<T, T>(c->ex, g.nn * nc, v, v, lslot(c, l, L_V));
-    // v = v / ||v||
-    vec_scale<T>(c->ex, g, nc, v, v, 1.0, lslot(c, l, L_V), lslot(c, l, L_T));
-    double lam = 0.0, lam_prev = 0.0;
-    int it = 0;
-    int vn = L_T;
-    for (it = 1; it <= c->opt.power_maxit; ++it) {
-        op_power<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), v, lslot(c, l, L_NUM),
-                    lslot(c, l, vn), q, lslot(c, l, L_PQ));
-        c->ge[l] += 1;
+    // Iteration k reads buf[(k-1) % 4] (k = 1: the start vector, in L.eig),
+    // writes its unnormalised image q_k = J(v_{k-1}/||v_{k-1}||) to
+    // buf[k % 4] and (v^T q, ||q_k||^2) to the slot pair pq[k % 3].  With at
+    // most two iterations queued beyond the one under test, neither its input
+    // nor its output is overwritten before the host has decided.
+    T *buf[4] = {P<T>(L.eig), P<T>(L.q), P<T>(L.t), P<T>(L.d[0])};
+    const int pq[3] = {L_PQ, L_PQB, L_PQC};
+    if (!c->have_eigs) vec_random<T>(c->ex, g, nc, c->opt.seed, l, buf[0], lslot(c, l, L_V));
+    else vec_dot<T, T>(c->ex, g.nn * nc, buf[0], buf[0], lslot(c, l, L_V));
+    const int maxit = c->opt.power_maxit;
+    const int ahead = power_lookahead(g.nn * nc);
+    int queued = 0;
+    auto queue = [&](int k) -> jfnk_status {
+        const double *n2 = k == 1 ? lslot(c, l, L_V) : lslot(c, l, pq[(k - 1) % 3] + 1);
+        double *out = lslot(c, l, pq[k % 3]);
+        op_power<T>(c->ex, mg_mode(c), g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), buf[(k - 1) % 4],
+                    lslot(c, l, L_NUM), n2, buf[k % 4], out);
         CHK(check_launch(c));
-        double pq[2];
-        CHK(read_slots(c, S_LEV + 16 * l + L_PQ, 2, pq));
-        lam = pq[0];
-        if (!(pq[1] > 0.0)) break;
-        const int vn2 = vn == L_T ? L_V : L_T;
-        vec_scale<T>(c->ex, g, nc, q, v, 1.0, lslot(c, l, L_PQ2), lslot(c, l, vn2));
-        vn = vn2;
+        HIPCHK(c, hipMemcpyAsync(c->hpin + 2 * (k % 3), out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipEventRecord(c->pev[k % 3], c->st));
+        queued = k;
+        return JFNK_OK;
+    };
+    double lam = 0.0, lam_prev = 0.0;
+    double n2_in = 0.0, n2_fin = 0.0;   // ||q||^2 of the input of iteration it / of the final image
+    int it = 0, fin = 0;                // fin: the iteration whose image is the eigenvector
+    bool zero = false;
+    for (it = 1; it <= maxit; ++it) {
+        while (queued < maxit && queued < it + ahead) CHK(queue(queued + 1));
+        HIPCHK(c, hipEventSynchronize(c->pev[it % 3]));
+        const double q_dot = c->hpin[2 * (it % 3)], q_n2 = c->hpin[2 * (it % 3) + 1];
+        c->ge[l] += 1;
+        lam = q_dot;
+        if (!(q_n2 > 0.0)) {       // J v = 0: keep v
+            zero = true;
+            break;
+        }
+        fin = it;
+        n2_fin = q_n2;
         if (!c->opt.power_fixed && it > 1 && std::fabs(lam - lam_prev) < c->opt.power_rtol * std::fabs(lam)) break;
         lam_prev = lam;
+        n2_in = q_n2;
     }
+    // the eigenvector estimate, normalised, into L.eig
+    if (zero && it == 1) vec_scale<T>(c->ex, g, nc, buf[0], buf[0], 1.0, lslot(c, l, L_V), nullptr);
+    else if (zero) vec_scale<T>(c->ex, g, nc, buf[(it - 1) % 4], buf[0], 1.0 / std::sqrt(n2_in), nullptr, nullptr);
+    else vec_scale<T>(c->ex, g, nc, buf[fin % 4], buf[0], 1.0 / std::sqrt(n2_fin), nullptr, nullptr);
     L.lam = lam;
-    L.power_iters = std::min(it, c->opt.power_maxit);
+    L.power_iters = std::min(it, maxit);
     if (!std::isfinite(lam)) return fail(c, JFNK_E_NONFINITE, "power method: non-finite eigenvalue estimate");
     return JFNK_OK;
 }
@@ -512,19 +549,16 @@ void vcycle(jfnk_ctx *c, int l, const T *b, T *s_out, double *s_out_n2, const do
     chebyshev<T>(c, l, b, s, c->opt.nu_post, false, s_out, s_out_n2);
 }
 
-// precondition: z = MG(v) with v FP64 on the finest level; ||z||^2 -> S_ZN2
-template <typename T> void precondition(jfnk_ctx *c, const double *v, T *z) {
+// precondition: z = MG(a v) with v FP64 on the finest level and
+// a = 1/sqrt(*rs) (rs null: a = 1); ||z||^2 -> S_ZN2
+template <typename T> void precondition(jfnk_ctx *c, const double *v, const double *rs, T *z) {
     Level &L = c->lev[c->L];
-    const T *b;
-    if (std::is_same<T, double>::value) {
-        b = (const T *)v;
-    } else {
-        vec_cast<double, T>(c->ex, L.g, c->nc, v, P<T>(L.b), lslot(c, c->L, L_B));
-        b = CP<T>(L.b);
-        vcycle<T>(c, c->L, b, z, slot(c, S_ZN2), lslot(c, c->L, L_B));
+    if (std::is_same<T, double>::value && rs == nullptr) {
+        vcycle<T>(c, c->L, (const T *)v, z, slot(c, S_ZN2));
         return;
     }
-    vcycle<T>(c, c->L, b, z, slot(c, S_ZN2));
+    vec_scale_cast<double, T>(c->ex, L.g, c->nc, v, P<T>(L.b), 1.0, rs, lslot(c, c->L, L_B));
+    vcycle<T>(c, c->L, CP<T>(L.b), z, slot(c, S_ZN2), lslot(c, c->L, L_B));
 }
 
 // ---------------------------------------------------------------------------
@@ -588,15 +622,20 @@ jfnk_status fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, doubl
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta;
         int k = 0;
+        // V_0 is normalised (sig_0 = 1); V_{j+1} is the orthogonalised w
+        // itself, its inverse norm sig_{j+1} written by the last pass
+        double *sig = slot(c, S_SIG);
+        vec_fill<double>(c->ex, sig, 1, 1.0);
         for (int j = 0; j < m; ++j) {
             T *zj = Z + (size_t)j * n;
-            precondition<T>(c, V + (size_t)j * n, zj);
+            double *Vj1 = V + (size_t)(j + 1) * n;
+            precondition<T>(c, V + (size_t)j * n, j == 0 ? nullptr : slot(c, S_W2), zj);
             CHK(apply_op<T>(c, op, zj, slot(c, S_ZN2), c->w));
             {
                 TimeScope ts(c, JFNK_TIMER_ARNOLDI, false);
-                arn_dots(c->ex, n, V, n, j + 1, c->w, slot(c, S_H1));
-                arn_update(c->ex, n, V, n, j + 1, slot(c, S_H1), c->w, slot(c, S_H2), nullptr);
-                arn_update(c->ex, n, V, n, j + 1, slot(c, S_H2), c->w, nullptr, slot(c, S_W2));
+                arn_dots(c->ex, n, V, n, j + 1, sig, c->w, slot(c, S_H1));
+                arn_update(c->ex, n, V, n, j + 1, sig, slot(c, S_H1), c->w, c->w, slot(c, S_H2), nullptr);
+                arn_update(c->ex, n, V, n, j + 1, sig, slot(c, S_H2), c->w, Vj1, nullptr, slot(c, S_W2));
             }
             CHK(check_launch(c));
             double hh[2 * MAXR + 1];
@@ -608,8 +647,6 @@ jfnk_status fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, doubl
             Hij(j + 1, j) = std::sqrt(hh[2 * MAXR]);
             if (!std::isfinite(Hij(j + 1, j))) return fail(c, JFNK_E_NONFINITE, "FGMRES: non-finite Arnoldi norm");
             const bool breakdown = Hij(j + 1, j) == 0.0;
-            if (!breakdown)
-                vec_scale<double>(c->ex, g, nc, c->w, V + (size_t)(j + 1) * n, 1.0 / Hij(j + 1, j), nullptr, nullptr);
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
                 Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
@@ -903,11 +940,13 @@ jfnk_status jfnk_create(const jfnk_problem *p, const jfnk_options *o, void *ws, 
         c->ex.lazy = &c->lazy;
     }
     for (int l = 0; l < JFNK_MAX_LEVELS; ++l) c->ge[l] = 0.0;
-    hipError_t e = hipMemsetAsync(c->scal, 0, NSLOT * sizeof(double), c->st);
+    hipError_t e = hipHostMalloc((void **)&c->hpin, 8 * sizeof(double), hipHostMallocDefault);
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&c->pev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemsetAsync(c->scal, 0, NSLOT * sizeof(double), c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
         g_err = std::string("jfnk_create: ") + hipGetErrorString(e);
-        delete c;
+        jfnk_destroy(c);
         return JFNK_E_DEVICE;
     }
     *out = c;
@@ -920,6 +959,9 @@ void jfnk_destroy(jfnk_ctx *c) {
         for (auto ev : t.ev) (void)hipEventDestroy(ev);
     if (c->t0) (void)hipEventDestroy(c->t0);
     if (c->t1) (void)hipEventDestroy(c->t1);
+    for (auto ev : c->pev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->hpin) (void)hipHostFree(c->hpin);
     delete c;
 }
 

@@ -122,6 +122,10 @@ void vec_cast(const Exec &, const Grid &, int nc, const TI *x, TO *y, double *nr
 template <typename T>
 void vec_scale(const Exec &, const Grid &, int nc, const T *x, T *y, double scale, const double *rs,
                double *nrm2);
+// y = a x on DoFs (0 on Dirichlet) in precision TO; a and nrm2 as in vec_scale
+template <typename TI, typename TO>
+void vec_scale_cast(const Exec &, const Grid &, int nc, const TI *x, TO *y, double scale, const double *rs,
+                    double *nrm2);
 // FD step numerator of a level: root (1 + ||x||) (mode 0) or root mean(1 + |x|) (mode 1)
 template <typename T>
 void vec_eps_num(const Exec &, const Grid &, int nc, const T *x, double root, int mode, double *num);
@@ -141,12 +145,16 @@ template <typename T> void vec_exp(const Exec &, long long n, const double *m, T
 template <typename TA, typename TB>
 void vec_dot(const Exec &, long long n, const TA *x, const TB *y, double *out);
 
-// Arnoldi (CGS2) on FP64 basis vectors V_0..V_{k-1} spaced by ld:
-// h_j = V_j . w
-void arn_dots(const Exec &, long long n, const double *V, long long ld, int k, const double *w, double *h);
-// w -= sum_j V_j h_j; then h2_j = V_j . w (h2 nullable) or ||w||^2 -> nrm2
-void arn_update(const Exec &, long long n, const double *V, long long ld, int k, const double *h, double *w,
-                double *h2, double *nrm2);
+// Arnoldi (CGS2) on FP64 basis vectors stored unnormalised: column j of the
+// orthonormal basis is sig_j V_j (V_j spaced by ld, sig_j a device slot).
+// h_j = sig_j V_j . w
+void arn_dots(const Exec &, long long n, const double *V, long long ld, int k, const double *sig, const double *w,
+              double *h);
+// wout = win - sum_j sig_j h_j V_j (wout may alias win); then
+// h2_j = sig_j V_j . wout (h2 non-null), or ||wout||^2 -> nrm2 and
+// 1/||wout|| -> sig_k (h2 null)
+void arn_update(const Exec &, long long n, const double *V, long long ld, int k, double *sig, const double *h,
+                const double *win, double *wout, double *h2, double *nrm2);
 // x += sum_j y_j Z_j (Z in TZ precision)
 template <typename TZ>
 void arn_combine(const Exec &, long long n, const TZ *Z, long long ld, int k, const double *y, double *x);

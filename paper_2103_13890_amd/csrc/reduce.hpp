@@ -86,11 +86,12 @@ struct FdStep {
     double fixed;                  // > 0: use this step
     const double *part = nullptr;  // deferred ||v||^2: partials of nb blocks
     int nb = 0;
-    // called by every thread of the block (a block-wide sum when deferred)
-    __device__ double eps() const {
-        if (fixed > 0.0) return fixed;
-        if (num == nullptr) return 0.0;
-        double n2;
+    // called by every thread of the block (a block-wide sum when deferred);
+    // n2out, when given, receives ||v||^2 (also with a fixed step)
+    __device__ double eps(double *n2out = nullptr) const {
+        if (!n2out && fixed > 0.0) return fixed;
+        if (!n2out && num == nullptr) return 0.0;
+        double n2 = 0.0;
         if (part) {
             __shared__ double scratch[MAX_WAVES];
             __shared__ double tot[1];
@@ -106,9 +107,12 @@ struct FdStep {
             double a[1] = {((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]))};
             block_sum<1>(a, scratch, tot);
             n2 = tot[0];
-        } else {
+        } else if (vn2) {
             n2 = *vn2;
         }
+        if (n2out) *n2out = n2;
+        if (fixed > 0.0) return fixed;
+        if (num == nullptr) return 0.0;
         return n2 > 0.0 ? *num / sqrt(n2) : 0.0;
     }
 };

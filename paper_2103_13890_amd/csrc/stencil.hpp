@@ -19,6 +19,8 @@
 // z-marching LDS-tiled form for large 3D levels.  Both share the element
 // routines and the epilogues.
 #pragma once
+#include <type_traits>
+
 #include "elem.hpp"
 #include "reduce.hpp"
 
@@ -245,6 +247,12 @@ template <typename T, int NC> struct EpiChebInit {
 };
 
 // power step: q = J v; v.q and ||q||^2 -> out[0..1]
+// Power step on an unnormalized direction v (Sec. 2, smoothers: the power
+// method).  With s = 1/||v||, the FD quotient is homogeneous in its
+// direction (the step scales as 1/||v||, so the perturbed state is the same),
+// J(s v) = s J(v): q = s J(v) is the image of the unit vector s v, and
+// s v^T q and ||q||^2 are its Rayleigh quotient and squared norm.  The
+// normalisation of the previous image thus needs no pass of its own.
 template <typename T, int NC> struct EpiPower {
     static constexpr int NS = 2;
     static constexpr int NCOMP = NC;
@@ -253,6 +261,8 @@ template <typename T, int NC> struct EpiPower {
     T *q;
     long long nn;
     double *out;
+    double sc = 0.0;     // 1/||v||, set on the device from the step's norm
+    __device__ __forceinline__ void prepare(double n2) { sc = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0; }
     __device__ __forceinline__ void load(long long i, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) in[c] = v[c * nn + i];
@@ -261,15 +271,30 @@ template <typename T, int NC> struct EpiPower {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const long long k = c * nn + i;
-            const T qk = dir ? T(0) : val[c];
+            const T qk = dir ? T(0) : (T)(sc * (double)val[c]);
             q[k] = qk;
-            sm[0] += (double)in[c] * (double)qk;
+            sm[0] += ((double)in[c] * sc) * (double)qk;
             sm[1] += (double)qk * (double)qk;
         }
     }
     __device__ void operator()(const double *t) const { out[0] = t[0]; out[1] = t[1]; }
     double *slot() const { return out; }
 };
+
+// epilogues that scale by 1/||v|| define prepare(||v||^2); the step and the
+// norm come from the same (possibly block-summed) value
+template <class E, class = void> struct EpiPrepares : std::false_type {};
+template <class E> struct EpiPrepares<E, std::void_t<decltype(&E::prepare)>> : std::true_type {};
+template <class E> __device__ __forceinline__ double fd_eps_prepare(const FdStep &fd, E &epi) {
+    if constexpr (EpiPrepares<E>::value) {
+        double n2 = 0.0;
+        const double e = fd.eps(&n2);
+        epi.prepare(n2);
+        return e;
+    } else {
+        return fd.eps();
+    }
+}
 
 // ---- one element in any mode ------------------------------------------------------
 // xe: state corners; ve: direction corners (FD modes); r: output contributions
@@ -415,7 +440,7 @@ template <int DIM, int KIND, int MODE, typename T, typename TV, class Epi>
 __global__ __launch_bounds__(BLOCK) void k_node(Grid g, Phys ph, const T *kap, const T *x, const TV *v, const T *Ax,
                                                 FdStep fd, Epi epi, Red red) {
     constexpr int NC = (KIND == JFNK_NEOHOOKE) ? 3 : 1;
-    const double eps = fd.eps();
+    const double eps = fd_eps_prepare(fd, epi);
     double sums[Epi::NS > 0 ? Epi::NS : 1];
 #pragma unroll
     for (int k = 0; k < (Epi::NS > 0 ? Epi::NS : 1); ++k) sums[k] = 0.0;

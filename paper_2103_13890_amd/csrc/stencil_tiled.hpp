@@ -78,7 +78,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     const int z0 = (int)((long long)tiz * g.NZ / ta.ntz), z1 = (int)((long long)(tiz + 1) * g.NZ / ta.ntz);
     const int rows = y1 - y0;
     const int t = threadIdx.x, nthr = blockDim.x;
-    const double eps = fd.eps();
+    const double eps = fd_eps_prepare(fd, epi);
     const bool zero_fd = FD && eps == 0.0;
     const T e = (T)eps;
     const T ie = eps > 0.0 ? (T)(1.0 / eps) : T(0);

@@ -64,6 +64,20 @@ template void vec_cast<double, float>(const Exec &, const Grid &, int, const dou
 template void vec_cast<float, double>(const Exec &, const Grid &, int, const float *, double *, double *);
 template void vec_cast<float, float>(const Exec &, const Grid &, int, const float *, float *, double *);
 
+template <typename TI, typename TO>
+void vec_scale_cast(const Exec &ex, const Grid &g, int nc, const TI *x, TO *y, double scale, const double *rs,
+                    double *nrm2) {
+    const int nb = vblocks(g.nn);
+    materialize(ex, const_cast<double *>(rs));
+    const Red r = red_for(ex, nrm2, nb);
+    k_scale<TI, TO><<<nb, BLOCK, 0, ex.st>>>(g, nc, x, y, scale, rs, r, nrm2);
+    if (nrm2) finish_to<1>(ex, nrm2, r, nb, FinStore<1>{nrm2});
+}
+template void vec_scale_cast<double, double>(const Exec &, const Grid &, int, const double *, double *, double,
+                                             const double *, double *);
+template void vec_scale_cast<double, float>(const Exec &, const Grid &, int, const double *, float *, double,
+                                            const double *, double *);
+
 template <typename T>
 void vec_scale(const Exec &ex, const Grid &g, int nc, const T *x, T *y, double scale, const double *rs,
                double *nrm2) {
@@ -282,14 +296,18 @@ __global__ __launch_bounds__(BLOCK) void k_arn_dots(long long n, const double *V
     block_partials<K>(s, red);
 }
 
-// w -= V h; then h2 = V^T w (H2) or ||w||^2 (!H2) as partials
+// wout = win - sum_j V_j (sig_j h_j); then h2 = V^T wout (H2) or ||wout||^2
+// (!H2) as partials.  The basis columns are stored unnormalised: column j is
+// sig_j V_j with sig_j its inverse norm, so a coefficient of the normalised
+// column is sig_j times one of the stored column.
 template <int K, bool H2>
 __global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double *V, long long ld, const double *h,
-                                                      double *w, Red red) {
+                                                      const double *sig, const double *win, double *wout,
+                                                      Red red) {
     constexpr int U = ArnUnroll<K>::U;
     constexpr int NS = H2 ? K : 1;
     __shared__ double hs[K];
-    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x] * sig[threadIdx.x];
     __syncthreads();
     double hj[K];
 #pragma unroll
@@ -300,7 +318,7 @@ __global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double 
     auto finish_one = [&](long long idx, double a, const double *vj) {
 #pragma unroll
         for (int j = 0; j < K; ++j) a -= hj[j] * vj[j];
-        w[idx] = a;
+        wout[idx] = a;
         if constexpr (H2) {
 #pragma unroll
             for (int j = 0; j < K; ++j) s[j] += vj[j] * a;
@@ -314,7 +332,7 @@ __global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double 
         double wi[U], vj[U][K];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            wi[u] = w[i + u * stride];
+            wi[u] = win[i + u * stride];
 #pragma unroll
             for (int j = 0; j < K; ++j) vj[u][j] = V[j * ld + i + u * stride];
         }
@@ -325,42 +343,53 @@ __global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double 
         double vj[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
-        finish_one(i, w[i], vj);
+        finish_one(i, win[i], vj);
     }
     block_partials<NS>(s, red);
 }
 
-struct FinStoreK {
+// h_j = sig_j t_j: dot products with the normalised columns
+struct FinScaleK {
     double *out;
+    const double *sig;
     int k;
     __device__ void operator()(const double *t) const {
-        for (int j = 0; j < k; ++j) out[j] = t[j];
+        for (int j = 0; j < k; ++j) out[j] = t[j] * sig[j];
+    }
+};
+// ||w||^2, and the inverse norm of w as the next column's sig
+struct FinNormSig {
+    double *out, *sig_next;
+    __device__ void operator()(const double *t) const {
+        out[0] = t[0];
+        sig_next[0] = t[0] > 0.0 ? 1.0 / sqrt(t[0]) : 0.0;
     }
 };
 
 static inline int arn_blocks(long long n) { return vblocks(n, 2048); }
 
-template <int K> void arn_dots_k(const Exec &ex, long long n, const double *V, long long ld, const double *w,
-                                 double *h) {
+template <int K> void arn_dots_k(const Exec &ex, long long n, const double *V, long long ld, const double *sig,
+                                 const double *w, double *h) {
     const int nb = arn_blocks(n);
     k_arn_dots<K><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, w, ex.red);
-    finish<K>(ex.st, ex.red, nb, FinStoreK{h, K});
+    finish<K>(ex.st, ex.red, nb, FinScaleK{h, sig, K});
 }
-template <int K> void arn_update_k(const Exec &ex, long long n, const double *V, long long ld, const double *h,
-                                   double *w, double *h2, double *nrm2) {
+template <int K> void arn_update_k(const Exec &ex, long long n, const double *V, long long ld, double *sig,
+                                   const double *h, const double *win, double *wout, double *h2, double *nrm2) {
     const int nb = arn_blocks(n);
     if (h2) {
-        k_arn_update<K, true><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, w, ex.red);
-        finish<K>(ex.st, ex.red, nb, FinStoreK{h2, K});
+        k_arn_update<K, true><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, sig, win, wout, ex.red);
+        finish<K>(ex.st, ex.red, nb, FinScaleK{h2, sig, K});
     } else {
-        k_arn_update<K, false><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, w, ex.red);
-        finish<1>(ex.st, ex.red, nb, FinStoreK{nrm2, 1});
+        k_arn_update<K, false><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, sig, win, wout, ex.red);
+        finish<1>(ex.st, ex.red, nb, FinNormSig{nrm2, sig + K});
     }
 }
 
-using DotsFn = void (*)(const Exec &, long long, const double *, long long, const double *, double *);
-using UpdFn = void (*)(const Exec &, long long, const double *, long long, const double *, double *, double *,
-                       double *);
+using DotsFn = void (*)(const Exec &, long long, const double *, long long, const double *, const double *,
+                        double *);
+using UpdFn = void (*)(const Exec &, long long, const double *, long long, double *, const double *,
+                       const double *, double *, double *, double *);
 template <int... Ks> constexpr std::array<DotsFn, sizeof...(Ks)> dots_table(std::integer_sequence<int, Ks...>) {
     return {&arn_dots_k<Ks + 1>...};
 }
@@ -370,14 +399,15 @@ template <int... Ks> constexpr std::array<UpdFn, sizeof...(Ks)> upd_table(std::i
 static constexpr auto kDots = dots_table(std::make_integer_sequence<int, ARN_MAX>{});
 static constexpr auto kUpd = upd_table(std::make_integer_sequence<int, ARN_MAX>{});
 
-void arn_dots(const Exec &ex, long long n, const double *V, long long ld, int k, const double *w, double *h) {
+void arn_dots(const Exec &ex, long long n, const double *V, long long ld, int k, const double *sig, const double *w,
+              double *h) {
     if (k < 1 || k > ARN_MAX) return;
-    kDots[k - 1](ex, n, V, ld, w, h);
+    kDots[k - 1](ex, n, V, ld, sig, w, h);
 }
-void arn_update(const Exec &ex, long long n, const double *V, long long ld, int k, const double *h, double *w,
-                double *h2, double *nrm2) {
+void arn_update(const Exec &ex, long long n, const double *V, long long ld, int k, double *sig, const double *h,
+                const double *win, double *wout, double *h2, double *nrm2) {
     if (k < 1 || k > ARN_MAX) return;
-    kUpd[k - 1](ex, n, V, ld, h, w, h2, nrm2);
+    kUpd[k - 1](ex, n, V, ld, sig, h, win, wout, h2, nrm2);
 }
 
 // x += Z y  (y passed by value)
