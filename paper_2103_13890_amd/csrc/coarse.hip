@@ -12,13 +12,18 @@ namespace jfnk {
 
 constexpr int CBLOCK = 1024;
 
-__device__ __forceinline__ double cg_bsum(double v) {
-    __shared__ double scratch[MAX_WAVES];
-    __shared__ double tot[1];
-    double a[1] = {v};
-    block_sum<1>(a, scratch, tot);
-    return tot[0];
-}
+// Block sum for the solver loops: one barrier per call, the wave totals in
+// one of two LDS arrays taken in turn (see block_sum1).  Every thread calls
+// it the same number of times, so the parity is uniform.
+struct CgSum {
+    int parity = 0;
+    __device__ __forceinline__ double operator()(double v) {
+        __shared__ double scratch[2][MAX_WAVES];
+        const double s = block_sum1(v, scratch[parity]);
+        parity ^= 1;
+        return s;
+    }
+};
 
 #define NODE_LOOP(i, n) for (long long i = threadIdx.x; i < (n); i += blockDim.x)
 
@@ -31,6 +36,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
     const long long ne = (long long)g.nx * g.ny * (DIM == 3 ? g.nz : 1);
     // r, p, q, then the element contributions ew[(c * ne + e) * NV + a]
     T *r = work, *p = work + n, *q = work + 2 * n, *ew = work + 3 * n;
+    CgSum cg_bsum;
     const double epsn = *num;
     const T h = (T)g.h;
     const double rnx = 1.0 / g.nx, rny = 1.0 / g.ny;
@@ -38,7 +44,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
     // q = (J - shift I) v via the FD quotient, given vv = v.v.  Every element
     // is evaluated once (its corner contributions go to ew); each node then
     // sums the contributions of its adjacent elements in a fixed order.
-    auto apply = [&](const T *v, double vv, double shift) {
+    auto apply = [&](const T *v, double vv, double shift) __attribute__((always_inline)) {
         const double eps = vv > 0.0 ? epsn / sqrt(vv) : 0.0;
         const T e = (T)eps;
         const bool zero_fd = eps == 0.0;
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
     long long fd = 0, iters = 0;
     bool s_nonzero = false;
 
-    auto cg = [&](double shift) -> double {
+    auto cg = [&](double shift) __attribute__((always_inline)) -> double {
         if (s_nonzero) {
             double ss = 0.0;
             NODE_LOOP(i, n) ss += (double)s[i] * (double)s[i];
@@ -194,6 +200,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
     T *sx = (T *)smem, *sv = sx + nn, *sk = sv + nn, *ew = sk + (INV ? nn : 0);
     const int i = threadIdx.x;
     const bool act = i < nn;
+    CgSum cg_bsum;
     const double epsn = *num;
     const T h = (T)g.h;
     int X = 0, Y = 0, Z = 0;
@@ -219,7 +226,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
     __syncthreads();
 
     // q_i = ((J - shift I) v)_i for the direction whose entry here is vi, vv = v.v
-    auto apply = [&](T vi, double vv, double shift) -> T {
+    auto apply = [&](T vi, double vv, double shift) __attribute__((always_inline)) -> T {
         const double eps = vv > 0.0 ? epsn / sqrt(vv) : 0.0;
         const T e = (T)eps;
         if (act) sv[i] = dir ? T(0) : vi;
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
     bool s_nonzero = false;
     T si = T(0), ri = T(0), pi = T(0), qi = T(0);
 
-    auto cg = [&](double shift) -> double {
+    auto cg = [&](double shift) __attribute__((always_inline)) -> double {
         if (s_nonzero) {
             const double ss = cg_bsum((double)si * (double)si);
             qi = apply(si, ss, shift);

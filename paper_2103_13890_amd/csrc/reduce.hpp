@@ -1,4 +1,4 @@
-// Deterministic reductions: 64-lane wavefront butterflies, a fixed-order
+// Deterministic reductions: 64-lane wavefront sums by DPP, a fixed-order
 // sum over the waves of a block, per-block partials, and a one-block
 // finishing kernel that sums the partials in block order.  No
 // floating-point atomics, so every result is bitwise reproducible for a
@@ -21,13 +21,35 @@ struct Red {
 template <int NS, class Fin>
 inline void finish(hipStream_t st, const Red &red, int nb, const Fin &fin);
 
+// Lane data movement within 16-lane rows (DPP), one 32-bit half at a time.
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active), the same value in
+// every lane.  Inside a 16-lane row each step adds the value of a partner
+// lane whose partner is the lane itself (lane ^ 1, lane ^ 2, then the
+// mirror images within 8 and 16 lanes), so both lanes of a pair form the
+// same IEEE sum; the four row sums are then added in a fixed order.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;   // identical in every lane: IEEE addition is commutative
+    v += dpp_mov<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);    // row_half_mirror
+    v += dpp_mov<0x140>(v);    // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Sum NS values over the block; the totals land in tot[0..NS) (shared).
+// blockDim.x must be a multiple of 64.
 template <int NS>
 __device__ __forceinline__ void block_sum(double (&v)[NS], double *scratch, double *tot) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -44,6 +66,21 @@ __device__ __forceinline__ void block_sum(double (&v)[NS], double *scratch, doub
         tot[threadIdx.x] = s;
     }
     __syncthreads();
+}
+
+// One value summed over the block with a single barrier: every thread reads
+// the wave totals (an LDS broadcast) and adds them in wave order.  scratch
+// (MAX_WAVES entries) must not be written again until every thread of the
+// block has passed a later barrier: callers that sum repeatedly alternate
+// two scratch arrays.
+__device__ __forceinline__ double block_sum1(double v, double *scratch) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += scratch[w];
+    return s;
 }
 
 // Per-block partial sums: the block's totals go to part[blockIdx.x * NS + k].
@@ -94,7 +131,6 @@ struct FdStep {
         double n2 = 0.0;
         if (part) {
             __shared__ double scratch[MAX_WAVES];
-            __shared__ double tot[1];
             // eight independent loads in flight per trip
             const int bd = blockDim.x;
             double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -104,9 +140,8 @@ struct FdStep {
                 for (int k = 0; k < 8; ++k) acc[k] += part[b + k * bd];
             }
             for (; b < nb; b += bd) acc[0] += part[b];
-            double a[1] = {((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]))};
-            block_sum<1>(a, scratch, tot);
-            n2 = tot[0];
+            n2 = block_sum1(((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])),
+                            scratch);
         } else if (vn2) {
             n2 = *vn2;
         }
