@@ -94,7 +94,9 @@ __device__ __forceinline__ T plap_pow(T base, double p, int which) {
 // scalar kinds: r[a] for one element.  w: state corners, kap: e^{m} corners
 // ---------------------------------------------------------------------------
 // m multiplies the whole element vector (0 switches an element off without
-// a branch).
+// a branch).  A switched-off element may have a degenerate state (no
+// gradient at delta = 0), so its nonlinear coefficient is selected away
+// rather than multiplied by 0.
 template <int DIM, int KIND, typename T, int PF = 0>
 __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys &ph, T h, T *r, T m = T(1)) {
     constexpr int NV = Cell<DIM>::NV;
@@ -129,6 +131,7 @@ __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys
         T s = quad * (T(1) / (T(KS) * h * h));
         T d2 = T(ph.a1) * T(ph.a1);
         T k = plap_pow<T, PF>(d2 + s, ph.a0, 0) * hk;
+        if (!(m != T(0))) k = T(0);
 #pragma unroll
         for (int a = 0; a < NV; ++a) r[a] = k * Ku[a];
     } else {  // INVCOEF
@@ -137,6 +140,7 @@ __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys
         for (int a = 0; a < NV; ++a) { ks += kap[a]; us += w[a]; }
         T kb = ks / T(NV), ub = us / T(NV);
         T k = kb * (T(1) + ub * ub) * hk;
+        if (!(m != T(0))) k = T(0);
 #pragma unroll
         for (int a = 0; a < NV; ++a) r[a] = k * Ku[a];
     }
@@ -253,7 +257,8 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
         kw = kb * (T(1) + wb * wb);
         dk = kb * vb * (T(2) * xb + eps * vb);
     }
-    const T cv = hk * kw, cx = hk * dk;
+    const bool on = m != T(0);
+    const T cv = on ? hk * kw : T(0), cx = on ? hk * dk : T(0);
 #pragma unroll
     for (int a = 0; a < NV; ++a) q[a] = cv * Kv[a] + cx * Kx[a];
 }

@@ -21,6 +21,7 @@
 #pragma once
 #include <type_traits>
 
+#include "access.hpp"
 #include "elem.hpp"
 #include "reduce.hpp"
 
@@ -28,9 +29,11 @@ namespace jfnk {
 
 // ---- epilogues ---------------------------------------------------------------
 // NS: number of grid sums; NCOMP: components; NIN: values read per node and
-// component.  load(i, in) reads them (issued ahead of the element work by
-// the tiled kernel), node(i, val, dir, sums, in) consumes val at node i;
-// operator()(totals) runs in the reduction's finishing kernel.
+// component.  load(at, in) reads them (issued ahead of the element work by
+// the tiled kernel), node(at, val, dir, sums, in) consumes val at the node;
+// at addresses the node (PtrAt or BufAt, access.hpp), the component c being
+// c * nn further on.  operator()(totals) runs in the reduction's finishing
+// kernel.
 
 // F = val - b (b nullable); Aout (nullable) receives val; ||F||^2 -> out
 template <typename T, int NC> struct EpiResidual {
@@ -42,16 +45,17 @@ template <typename T, int NC> struct EpiResidual {
     T *Aout;
     long long nn;
     double *out;
-    __device__ __forceinline__ void load(long long i, T *in) const {
+    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) in[c] = b ? b[c * nn + i] : T(0);
+        for (int c = 0; c < NC; ++c) in[c] = b ? at.ld(b, c * nn) : T(0);
     }
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *s, const T *in) const {
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *s, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             T f = dir ? T(0) : val[c] - in[c];
-            F[c * nn + i] = f;
-            if (Aout) Aout[c * nn + i] = dir ? T(0) : val[c];
+            at.st(F, c * nn, f);
+            if (Aout) at.st(Aout, c * nn, dir ? T(0) : val[c]);
             s[0] += (double)f * (double)f;
         }
     }
@@ -66,10 +70,11 @@ template <typename T, int NC> struct EpiJv {
     static constexpr int NIN = 0;
     T *Jv;
     long long nn;
-    __device__ __forceinline__ void load(long long, T *) const {}
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *, const T *) const {
+    template <class At> __device__ __forceinline__ void load(const At &, T *) const {}
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *, const T *) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) Jv[c * nn + i] = dir ? T(0) : val[c];
+        for (int c = 0; c < NC; ++c) at.st(Jv, c * nn, dir ? T(0) : val[c]);
     }
     __device__ void operator()(const double *) const {}
     double *slot() const { return nullptr; }
@@ -86,30 +91,26 @@ template <typename T, int NC> struct EpiCheb {
     T c1, c2;
     long long nn;
     double *out;
-    __device__ __forceinline__ void load(long long i, T *in) const {
+    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
-            in[3 * c] = d[k];
-            in[3 * c + 1] = r[k];
-            in[3 * c + 2] = s[k];
+            in[3 * c] = at.ld(d, c * nn);
+            in[3 * c + 1] = at.ld((const T *)r, c * nn);
+            in[3 * c + 2] = at.ld((const T *)s, c * nn);
         }
     }
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
-            if (dir) {
-                r[k] = T(0); s[k] = T(0); dn[k] = T(0);
-                continue;
-            }
+            const long long k = c * nn;
             const T dk = in[3 * c];
-            s[k] = in[3 * c + 2] + dk;
             const T rk = in[3 * c + 1] - val[c];
-            r[k] = rk;
             const T dnew = c1 * dk + c2 * rk;
-            dn[k] = dnew;
-            sm[0] += (double)dnew * (double)dnew;
+            at.st(s, k, dir ? T(0) : in[3 * c + 2] + dk);
+            at.st(r, k, dir ? T(0) : rk);
+            at.st(dn, k, dir ? T(0) : dnew);
+            if (!dir) sm[0] += (double)dnew * (double)dnew;
         }
     }
     __device__ void operator()(const double *t) const { out[0] = t[0]; }
@@ -130,25 +131,22 @@ template <typename T, int NC> struct EpiChebFirst {
     T inv_theta, c1, c2;
     long long nn;
     double *out;
-    __device__ __forceinline__ void load(long long i, T *in) const {
+    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) in[c] = b[c * nn + i];
+        for (int c = 0; c < NC; ++c) in[c] = at.ld(b, c * nn);
     }
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
-            if (dir) {
-                r[k] = T(0); s[k] = T(0); dn[k] = T(0);
-                continue;
-            }
+            const long long k = c * nn;
             const T d0 = in[c] * inv_theta;
-            s[k] = d0;
             const T rk = in[c] - val[c] * inv_theta;
-            r[k] = rk;
             const T dnew = c1 * d0 + c2 * rk;
-            dn[k] = dnew;
-            sm[0] += (double)dnew * (double)dnew;
+            at.st(s, k, dir ? T(0) : d0);
+            at.st(r, k, dir ? T(0) : rk);
+            at.st(dn, k, dir ? T(0) : dnew);
+            if (!dir) sm[0] += (double)dnew * (double)dnew;
         }
     }
     __device__ void operator()(const double *t) const { out[0] = t[0]; }
@@ -167,28 +165,23 @@ template <typename T, int NC> struct EpiChebLast {
     T c1, c2;
     long long nn;
     double *out;
-    __device__ __forceinline__ void load(long long i, T *in) const {
+    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
-            in[3 * c] = d[k];
-            in[3 * c + 1] = r[k];
-            in[3 * c + 2] = s[k];
+            in[3 * c] = at.ld(d, c * nn);
+            in[3 * c + 1] = at.ld(r, c * nn);
+            in[3 * c + 2] = at.ld(s, c * nn);
         }
     }
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
-            if (dir) {
-                sout[k] = T(0);
-                continue;
-            }
             const T dk = in[3 * c];
             const T rk = in[3 * c + 1] - val[c];
             const T dnew = c1 * dk + c2 * rk;
-            const T so = (in[3 * c + 2] + dk) + dnew;
-            sout[k] = so;
+            const T so = dir ? T(0) : (in[3 * c + 2] + dk) + dnew;
+            at.st(sout, c * nn, so);
             sm[0] += (double)so * (double)so;
         }
     }
@@ -204,13 +197,14 @@ template <typename T, int NC> struct EpiResidJv {
     const T *b;
     T *t;
     long long nn;
-    __device__ __forceinline__ void load(long long i, T *in) const {
+    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) in[c] = b[c * nn + i];
+        for (int c = 0; c < NC; ++c) in[c] = at.ld(b, c * nn);
     }
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *, const T *in) const {
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *, const T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) t[c * nn + i] = dir ? T(0) : in[c] - val[c];
+        for (int c = 0; c < NC; ++c) at.st(t, c * nn, dir ? T(0) : in[c] - val[c]);
     }
     __device__ void operator()(const double *) const {}
     double *slot() const { return nullptr; }
@@ -226,19 +220,19 @@ template <typename T, int NC> struct EpiChebInit {
     T inv_theta;
     long long nn;
     double *out;
-    __device__ __forceinline__ void load(long long i, T *in) const {
+    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) in[c] = b[c * nn + i];
+        for (int c = 0; c < NC; ++c) in[c] = at.ld(b, c * nn);
     }
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
-            if (dir) { r[k] = T(0); d[k] = T(0); continue; }
-            const T rk = in[c] - val[c];
-            r[k] = rk;
+            const long long k = c * nn;
+            const T rk = dir ? T(0) : in[c] - val[c];
             const T dk = rk * inv_theta;
-            d[k] = dk;
+            at.st(r, k, rk);
+            at.st(d, k, dk);
             sm[0] += (double)dk * (double)dk;
         }
     }
@@ -246,7 +240,6 @@ template <typename T, int NC> struct EpiChebInit {
     double *slot() const { return out; }
 };
 
-// power step: q = J v; v.q and ||q||^2 -> out[0..1]
 // Power step on an unnormalized direction v (Sec. 2, smoothers: the power
 // method).  With s = 1/||v||, the FD quotient is homogeneous in its
 // direction (the step scales as 1/||v||, so the perturbed state is the same),
@@ -263,16 +256,16 @@ template <typename T, int NC> struct EpiPower {
     double *out;
     double sc = 0.0;     // 1/||v||, set on the device from the step's norm
     __device__ __forceinline__ void prepare(double n2) { sc = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0; }
-    __device__ __forceinline__ void load(long long i, T *in) const {
+    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) in[c] = v[c * nn + i];
+        for (int c = 0; c < NC; ++c) in[c] = at.ld(v, c * nn);
     }
-    __device__ __forceinline__ void node(long long i, const T *val, bool dir, double *sm, const T *in) const {
+    template <class At>
+    __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *sm, const T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const long long k = c * nn + i;
             const T qk = dir ? T(0) : (T)(sc * (double)val[c]);
-            q[k] = qk;
+            at.st(q, c * nn, qk);
             sm[0] += ((double)in[c] * sc) * (double)qk;
             sm[1] += (double)qk * (double)qk;
         }
@@ -454,8 +447,9 @@ __global__ __launch_bounds__(BLOCK) void k_node(Grid g, Phys ph, const T *kap, c
         for (int c = 0; c < NC; ++c) val[c] = T(0);
         if (!dir) node_value<DIM, KIND, MODE, T, TV>(g, ph, kap, x, v, Ax, eps, X, Y, Z, i, val);
         T in[Epi::NIN * NC > 0 ? Epi::NIN * NC : 1];
-        epi.load(i, in);
-        epi.node(i, val, dir, sums, in);
+        const PtrAt at{i};
+        epi.load(at, in);
+        epi.node(at, val, dir, sums, in);
     }
     if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
 }

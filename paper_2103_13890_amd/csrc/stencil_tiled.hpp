@@ -95,9 +95,27 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     auto ydir = [&](int gy) { return ((g.dir & JFNK_FACE_YLO) && gy == 0) || ((g.dir & JFNK_FACE_YHI) && gy == g.ny); };
     auto zdir = [&](int gz) { return ((g.dir & JFNK_FACE_ZLO) && gz == 0) || ((g.dir & JFNK_FACE_ZHI) && gz == g.nz); };
 
+    // Block-uniform row flags, bit r for the LDS row r (grid row y0 - 1 + r):
+    // rfree: inside the grid and not a Dirichlet row (direction entries are
+    // free there); eok: element row y0 - 1 + r inside the grid; odir: output
+    // row y0 + r on a Dirichlet face.  Lane factors: vlane switches off the
+    // direction entries of a column outside the grid or on a Dirichlet face
+    // in x, elane the element of a column outside the grid.
+    unsigned rfree = 0, eok = 0, odir = 0;
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+        const int gy = y0 - 1 + r;
+        if (gy >= 0 && gy < g.NY && !ydir(gy)) rfree |= 1u << r;
+        if (r <= R && gy >= 0 && gy < g.ny) eok |= 1u << r;
+        if (r < R && ydir(y0 + r)) odir |= 1u << r;
+    }
+    const TV vlane = (own_col && !xdir_t) ? TV(1) : TV(0);
+    const T elane = own_elem ? T(1) : T(0);
+
     // ---- plane fetch (global -> registers) and store (registers -> LDS) ----
-    // Loads use clamped indices and are always issued; values outside the
-    // grid (or on Dirichlet nodes, for v) are replaced by zero afterwards.
+    // Loads use clamped rows and columns and are always issued.  Off the grid
+    // the state is a copy of the edge row or plane, read only by elements that
+    // are switched off; the direction is zeroed there and on Dirichlet nodes.
     const int tc = t < g.NX ? t : g.NX - 1;
     T px[R + 2], pk[R + 2], qx = T(0), qk = T(0);
     TV pv[R + 2], qv = TV(0);
@@ -105,22 +123,18 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         const int pzc = pz < 0 ? 0 : (pz >= g.NZ ? g.NZ - 1 : pz);
         const bool zin = pz == pzc;
         const bool zd = zdir(pz);
+        const bool zfree = zin && !zd;
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
             const int gy = y0 - 1 + r;
             const int gyc = gy < 0 ? 0 : (gy >= g.NY ? g.NY - 1 : gy);
-            const bool in = zin && gy == gyc && own_col;
-            const int idx = (pzc * g.NY + gyc) * g.NX + tc;
-            const T xv = x[idx];
-            px[r] = in ? xv : T(0);
+            const BufAt at{(unsigned)((pzc * g.NY + gyc) * g.NX), (unsigned)tc};
+            px[r] = at.ld(x, 0);
             if constexpr (FD) {
-                const TV vv = v[idx];
-                pv[r] = (in && !(xdir_t || zd || ydir(gy))) ? vv : TV(0);
+                const TV vv = at.ld(v, 0);
+                pv[r] = (zfree && ((rfree >> r) & 1u)) ? vv * vlane : TV(0);
             }
-            if constexpr (INV) {
-                const T kv = kap[idx];
-                pk[r] = in ? kv : T(0);
-            }
+            if constexpr (INV) pk[r] = at.ld(kap, 0);
         }
         if (extra) {       // column nx, row t
             const int gy = y0 - 1 + t;
@@ -169,7 +183,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
     for (int k = 0; k < R; ++k) { C0[k] = T(0); C1[k] = T(0); O[k] = T(0); }
     auto layer = [&](int ez) {
-        const bool lz = !zero_fd && ez >= 0 && ez < g.nz && own_elem;
+        const bool lz = !zero_fd && ez >= 0 && ez < g.nz;
         const int lo = (ez & 1) * plane + t, hi = ((ez + 1) & 1) * plane + t;
         // corners on the current row: [plane lo/hi][column t / t+1]
         T cx[4], ck[4];
@@ -194,10 +208,9 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { uk[c] = T(0); uv[c] = TV(0); }
                 row(re + 1, ux, uv, uk);
-                // element rows outside the grid read zero-filled halo rows and are
-                // switched off by the factor m (no branch)
-                const int ey = y0 - 1 + re;
-                const T m = (ey >= 0 && ey < g.ny) ? T(1) : T(0);
+                // element rows and columns outside the grid are switched off by
+                // the factor m (no branch); their corners hold finite copies
+                const T m = ((eok >> re) & 1u) ? elane : T(0);
                 // corner a = ax + 2 ay + 4 az
                 const T xe[1][8] = {{cx[0], cx[1], ux[0], ux[1], cx[2], cx[3], ux[2], ux[3]}};
                 T ve[1][8], kp[8];
@@ -225,6 +238,17 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     };
 
     if (t < R) xb[t * P] = T(0);        // node column 0 has no left element
+    // columns NX..P-1 of every plane row: read as corners by the lanes past
+    // the last element column, so they must hold finite values
+    if (P > g.NX) {
+        const int pad = P - g.NX;
+        for (int q = t; q < 2 * ta.srows * pad; q += nthr) {
+            const int o = (q / pad) * P + g.NX + q % pad;
+            sx[o] = T(0);
+            if constexpr (FD) sv[o] = TV(0);
+            if constexpr (INV) sk[o] = T(0);
+        }
+    }
 
     // prologue: planes z0-1 and z0 in LDS, plane z0+1 in registers
     fetch(z0 - 1);
@@ -249,15 +273,15 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int kc = k < rows ? k : rows - 1;
-                const long long i = (long long)((z * g.NY + y0 + kc) * g.NX + tc);
-                epi.load(i, pin[k]);
-                pax[k] = PLAIN ? Ax[i] : T(0);
+                const BufAt at{(unsigned)((z * g.NY + y0 + kc) * g.NX), (unsigned)tc};
+                epi.load(at, pin[k]);
+                pax[k] = PLAIN ? at.ld(Ax, 0) : T(0);
             }
             if (extra) {
                 const int kc = t < rows ? t : rows - 1;
-                const long long i = (long long)((z * g.NY + y0 + kc) * g.NX + g.nx);
-                epi.load(i, qin);
-                if constexpr (PLAIN) qax = Ax[i];
+                const PtrAt at{(long long)((z * g.NY + y0 + kc) * g.NX + g.nx)};
+                epi.load(at, qin);
+                if constexpr (PLAIN) qax = at.ld(Ax, 0);
             }
         }
         layer(z);
@@ -270,20 +294,20 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                 if (k >= rows) break;
                 const int gy = y0 + k;
                 if (own_col) {
-                    const long long i = (long long)((z * g.NY + gy) * g.NX + t);
-                    const bool dir = zd || ydir(gy) || xdir_t;
+                    const BufAt at{(unsigned)((z * g.NY + gy) * g.NX), (unsigned)t};
+                    const bool dir = zd || ((odir >> k) & 1u) || xdir_t;
                     T val[1] = {T(0)};
                     if (!dir && !zero_fd) {
                         T acc = O[k] + xb[k * P + t];
                         if constexpr (PLAIN) acc = (acc - pax[k]) * ie;
                         val[0] = acc;
                     }
-                    epi.node(i, val, dir, sums, pin[k]);
+                    epi.node(at, val, dir, sums, pin[k]);
                 }
             }
             if (extra && t < rows) {
                 const int gy = y0 + t;
-                const long long i = (long long)((z * g.NY + gy) * g.NX + g.nx);
+                const PtrAt at{(long long)((z * g.NY + gy) * g.NX + g.nx)};
                 const bool dir = zd || ydir(gy) || xdir_e;
                 T val[1] = {T(0)};
                 if (!dir && !zero_fd) {
@@ -291,7 +315,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                     if constexpr (PLAIN) acc = (acc - qax) * ie;
                     val[0] = acc;
                 }
-                epi.node(i, val, dir, sums, qin);
+                epi.node(at, val, dir, sums, qin);
             }
         }
         __syncthreads();
