@@ -41,14 +41,20 @@ struct PtrAt {
     template <typename T> __device__ __forceinline__ void st(T *p, long long c, T v) const { p[c + i] = v; }
 };
 
+// row must be the same in every lane: it is read from the first active lane
+// (a plain copy when the compiler already holds it in a scalar register;
+// otherwise the read keeps it from looping over distinct lane values).
 struct BufAt {
     unsigned row;   // index of the row's first node (block-uniform)
     unsigned col;   // the lane's column
+    template <typename T> __device__ __forceinline__ unsigned soff(long long c) const {
+        return __builtin_amdgcn_readfirstlane((row + (unsigned)c) * (unsigned)sizeof(T));
+    }
     template <typename T> __device__ __forceinline__ T ld(const T *p, long long c) const {
-        return buf_ld<T>(p, col * (unsigned)sizeof(T), (row + (unsigned)c) * (unsigned)sizeof(T));
+        return buf_ld<T>(p, col * (unsigned)sizeof(T), soff<T>(c));
     }
     template <typename T> __device__ __forceinline__ void st(T *p, long long c, T v) const {
-        buf_st<T>(p, col * (unsigned)sizeof(T), (row + (unsigned)c) * (unsigned)sizeof(T), v);
+        buf_st<T>(p, col * (unsigned)sizeof(T), soff<T>(c), v);
     }
 };
 

@@ -112,40 +112,61 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     const TV vlane = (own_col && !xdir_t) ? TV(1) : TV(0);
     const T elane = own_elem ? T(1) : T(0);
 
+    // Block-uniform scalars used inside the plane loop.  They pass an empty
+    // register barrier at the top of every iteration, so what the compiler
+    // derives from them (row offsets, row and face tests) is recomputed there
+    // by scalar instructions instead of being kept live, as dozens of scalar
+    // registers, across the loop.
+    auto sc = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+    int uNX = sc(g.NX), uNY = sc(g.NY), uNZ = sc(g.NZ), unx = sc(g.nx), unz = sc(g.nz), udir = sc(g.dir);
+    int uy0 = sc(y0), urows = sc(rows);
+    unsigned ufree = sc(rfree), ueok = sc(eok), uodir = sc(odir);
+    // (the barrier's outputs count as divergent to the compiler, hence the
+    // lane reads that mark them uniform again; on scalar registers they are
+    // plain copies)
+    auto refresh = [&]() {
+        asm volatile("" : "+s"(uNX), "+s"(uNY), "+s"(uNZ), "+s"(unx), "+s"(unz), "+s"(udir), "+s"(uy0),
+                     "+s"(urows), "+s"(ufree), "+s"(ueok), "+s"(uodir));
+        uNX = sc(uNX); uNY = sc(uNY); uNZ = sc(uNZ); unx = sc(unx); unz = sc(unz); udir = sc(udir);
+        uy0 = sc(uy0); urows = sc(urows); ufree = sc(ufree); ueok = sc(ueok); uodir = sc(uodir);
+    };
+    auto zdir_u = [&](int gz) { return ((udir & JFNK_FACE_ZLO) && gz == 0) || ((udir & JFNK_FACE_ZHI) && gz == unz); };
+    auto ydir_u = [&](int gy) { return ((udir & JFNK_FACE_YLO) && gy == 0) || ((udir & JFNK_FACE_YHI) && gy == uNY - 1); };
+
     // ---- plane fetch (global -> registers) and store (registers -> LDS) ----
-    // Loads use clamped rows and columns and are always issued.  Off the grid
+    // Loads use clamped urows and columns and are always issued.  Off the grid
     // the state is a copy of the edge row or plane, read only by elements that
     // are switched off; the direction is zeroed there and on Dirichlet nodes.
-    const int tc = t < g.NX ? t : g.NX - 1;
+    const int tc = t < uNX ? t : uNX - 1;
     T px[R + 2], pk[R + 2], qx = T(0), qk = T(0);
     TV pv[R + 2], qv = TV(0);
     auto fetch = [&](int pz) {
-        const int pzc = pz < 0 ? 0 : (pz >= g.NZ ? g.NZ - 1 : pz);
+        const int pzc = pz < 0 ? 0 : (pz >= uNZ ? uNZ - 1 : pz);
         const bool zin = pz == pzc;
-        const bool zd = zdir(pz);
+        const bool zd = zdir_u(pz);
         const bool zfree = zin && !zd;
 #pragma unroll
         for (int r = 0; r < R + 2; ++r) {
-            const int gy = y0 - 1 + r;
-            const int gyc = gy < 0 ? 0 : (gy >= g.NY ? g.NY - 1 : gy);
-            const BufAt at{(unsigned)((pzc * g.NY + gyc) * g.NX), (unsigned)tc};
+            const int gy = uy0 - 1 + r;
+            const int gyc = gy < 0 ? 0 : (gy >= uNY ? uNY - 1 : gy);
+            const BufAt at{(unsigned)((pzc * uNY + gyc) * uNX), (unsigned)tc};
             px[r] = at.ld(x, 0);
             if constexpr (FD) {
                 const TV vv = at.ld(v, 0);
-                pv[r] = (zfree && ((rfree >> r) & 1u)) ? vv * vlane : TV(0);
+                pv[r] = (zfree && ((ufree >> r) & 1u)) ? vv * vlane : TV(0);
             }
             if constexpr (INV) pk[r] = at.ld(kap, 0);
         }
         if (extra) {       // column nx, row t
-            const int gy = y0 - 1 + t;
-            const int gyc = gy < 0 ? 0 : (gy >= g.NY ? g.NY - 1 : gy);
-            const bool in = zin && gy == gyc && t < rows + 2;
-            const int idx = (pzc * g.NY + gyc) * g.NX + g.nx;
+            const int gy = uy0 - 1 + t;
+            const int gyc = gy < 0 ? 0 : (gy >= uNY ? uNY - 1 : gy);
+            const bool in = zin && gy == gyc && t < urows + 2;
+            const int idx = (pzc * uNY + gyc) * uNX + unx;
             const T xv = x[idx];
             qx = in ? xv : T(0);
             if constexpr (FD) {
                 const TV vv = v[idx];
-                qv = (in && !(xdir_e || zd || ydir(gy))) ? vv : TV(0);
+                qv = (in && !(xdir_e || zd || ydir_u(gy))) ? vv : TV(0);
             }
             if constexpr (INV) {
                 const T kv = kap[idx];
@@ -158,24 +179,24 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         if (own_col) {
 #pragma unroll
             for (int r = 0; r < R + 2; ++r) {
-                if (r < rows + 2) {
+                if (r < urows + 2) {
                     sx[sl * plane + r * P + t] = px[r];
                     if constexpr (FD) sv[sl * plane + r * P + t] = pv[r];
                     if constexpr (INV) sk[sl * plane + r * P + t] = pk[r];
                 }
             }
         }
-        if (extra && t < rows + 2) {
-            sx[sl * plane + t * P + g.nx] = qx;
-            if constexpr (FD) sv[sl * plane + t * P + g.nx] = qv;
-            if constexpr (INV) sk[sl * plane + t * P + g.nx] = qk;
+        if (extra && t < urows + 2) {
+            sx[sl * plane + t * P + unx] = qx;
+            if constexpr (FD) sv[sl * plane + t * P + unx] = qv;
+            if constexpr (INV) sk[sl * plane + t * P + unx] = qk;
         }
     };
 
     // ---- element layer ez, walked row by row --------------------------------
     // C0/C1[k]: contributions of the layer below to node row y0 + k, columns
     // t and t + 1 (the carry); O[k]: the finished value of column t.  The walk
-    // over the element rows is unrolled, so all indices are compile-time; a
+    // over the element urows is unrolled, so all indices are compile-time; a
     // row k is finished when element row k + 1 is done, and its carry slot
     // then takes this layer's contribution to the plane above.  The part for
     // column t + 1 goes to the hand-over buffer.
@@ -183,7 +204,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
     for (int k = 0; k < R; ++k) { C0[k] = T(0); C1[k] = T(0); O[k] = T(0); }
     auto layer = [&](int ez) {
-        const bool lz = !zero_fd && ez >= 0 && ez < g.nz;
+        const bool lz = !zero_fd && ez >= 0 && ez < unz;
         const int lo = (ez & 1) * plane + t, hi = ((ez + 1) & 1) * plane + t;
         // corners on the current row: [plane lo/hi][column t / t+1]
         T cx[4], ck[4];
@@ -200,7 +221,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         T pS0 = T(0), pS1 = T(0), pN0 = T(0), pN1 = T(0);
 #pragma unroll
         for (int re = 0; re <= R; ++re) {
-            if (re > rows) break;
+            if (re > urows) break;
             T r8[1][8];
             if (lz) {
                 T ux[4], uk[4];
@@ -208,9 +229,9 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { uk[c] = T(0); uv[c] = TV(0); }
                 row(re + 1, ux, uv, uk);
-                // element rows and columns outside the grid are switched off by
+                // element urows and columns outside the grid are switched off by
                 // the factor m (no branch); their corners hold finite copies
-                const T m = ((eok >> re) & 1u) ? elane : T(0);
+                const T m = ((ueok >> re) & 1u) ? elane : T(0);
                 // corner a = ax + 2 ay + 4 az
                 const T xe[1][8] = {{cx[0], cx[1], ux[0], ux[1], cx[2], cx[3], ux[2], ux[3]}};
                 T ve[1][8], kp[8];
@@ -231,7 +252,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                 const T t1 = C1[k] + (pS1 + r8[0][1]);
                 C0[k] = pN0 + r8[0][4];
                 C1[k] = pN1 + r8[0][5];
-                if (own_elem && k < rows) xb[k * P + t + 1] = t1;
+                if (own_elem && k < urows) xb[k * P + t + 1] = t1;
             }
             pS0 = r8[0][2]; pS1 = r8[0][3]; pN0 = r8[0][6]; pN1 = r8[0][7];
         }
@@ -266,20 +287,21 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     constexpr int NIN = Epi::NIN > 0 ? Epi::NIN : 1;
     constexpr bool PLAIN = MODE == M_FD_PLAIN;
     for (int z = z0 - 1; z < z1; ++z) {
+        refresh();
         T pin[R][NIN], pax[R], qin[NIN], qax = T(0);
         if (z >= z0) {
             if (z + 2 <= z1) fetch(z + 2);
             // clamped row and column: always a valid node, unused where out of the tile
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const int kc = k < rows ? k : rows - 1;
-                const BufAt at{(unsigned)((z * g.NY + y0 + kc) * g.NX), (unsigned)tc};
+                const int kc = k < urows ? k : urows - 1;
+                const BufAt at{(unsigned)((z * uNY + uy0 + kc) * uNX), (unsigned)tc};
                 epi.load(at, pin[k]);
                 pax[k] = PLAIN ? at.ld(Ax, 0) : T(0);
             }
             if (extra) {
-                const int kc = t < rows ? t : rows - 1;
-                const PtrAt at{(long long)((z * g.NY + y0 + kc) * g.NX + g.nx)};
+                const int kc = t < urows ? t : urows - 1;
+                const PtrAt at{(long long)((z * uNY + uy0 + kc) * uNX + unx)};
                 epi.load(at, qin);
                 if constexpr (PLAIN) qax = at.ld(Ax, 0);
             }
@@ -288,14 +310,14 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         __syncthreads();
         if (z + 2 <= z1) store(z + 2);
         if (z >= z0) {
-            const bool zd = zdir(z);
+            const bool zd = zdir_u(z);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                if (k >= rows) break;
-                const int gy = y0 + k;
+                if (k >= urows) break;
+                const int gy = uy0 + k;
                 if (own_col) {
-                    const BufAt at{(unsigned)((z * g.NY + gy) * g.NX), (unsigned)t};
-                    const bool dir = zd || ((odir >> k) & 1u) || xdir_t;
+                    const BufAt at{(unsigned)((z * uNY + gy) * uNX), (unsigned)t};
+                    const bool dir = zd || ((uodir >> k) & 1u) || xdir_t;
                     T val[1] = {T(0)};
                     if (!dir && !zero_fd) {
                         T acc = O[k] + xb[k * P + t];
@@ -305,13 +327,13 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                     epi.node(at, val, dir, sums, pin[k]);
                 }
             }
-            if (extra && t < rows) {
-                const int gy = y0 + t;
-                const PtrAt at{(long long)((z * g.NY + gy) * g.NX + g.nx)};
-                const bool dir = zd || ydir(gy) || xdir_e;
+            if (extra && t < urows) {
+                const int gy = uy0 + t;
+                const PtrAt at{(long long)((z * uNY + gy) * uNX + unx)};
+                const bool dir = zd || ydir_u(gy) || xdir_e;
                 T val[1] = {T(0)};
                 if (!dir && !zero_fd) {
-                    T acc = xb[t * P + g.nx];
+                    T acc = xb[t * P + unx];
                     if constexpr (PLAIN) acc = (acc - qax) * ie;
                     val[0] = acc;
                 }
