@@ -759,6 +759,11 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
     rep->fnorm0 = f0;
     rep->fnorm = f0;
     double fn = f0;
+    // energy merit of the current iterate, kept from the accepted trial point
+    // of the previous step (the same kernels on the same data: bitwise equal
+    // to evaluating it again)
+    bool psi_known = false;
+    double psi_u = 0.0;
     for (int k = 0; k <= o.newton_maxit; ++k) {
         if (!std::isfinite(fn)) return fail(c, JFNK_E_NONFINITE, "Newton: non-finite residual norm");
         if (fn <= std::max(o.newton_atol, o.newton_rtol * f0)) return JFNK_OK;
@@ -780,7 +785,8 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
         const bool use_e = variational(c->prob.kind) && o.merit == JFNK_MERIT_AUTO && slope_e < 0.0;
         double phi0, slope;
         if (use_e) {
-            CHK(merit_energy(c, c->u, &phi0));
+            if (!psi_known) CHK(merit_energy(c, c->u, &psi_u));
+            phi0 = psi_u;
             slope = slope_e;
         } else {
             phi0 = 0.5 * fn * fn;
@@ -788,14 +794,13 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
         }
         double alpha = 1.0, ap = 0.0, pp = 0.0;
         bool have_prev = false, accepted = false;
-        double fnt = 0.0;
+        double fnt = 0.0, ph = 0.0;
         for (int it = 1; it <= o.ls_maxit; ++it) {
             vec_axpy(c->ex, c->n, c->u, alpha, c->dx, c->ut);
             CHK(eval_residual(c, c->ut, c->Ft, c->Aut, S_FT2, true));
             double ft2;
             CHK(read_slots(c, S_FT2, 1, &ft2));
             fnt = std::sqrt(ft2);
-            double ph;
             if (use_e) CHK(merit_energy(c, c->ut, &ph));
             else ph = 0.5 * ft2;
             if (std::isfinite(ph) && ph <= phi0 + o.armijo * alpha * slope) { accepted = true; break; }
@@ -808,6 +813,8 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
             alpha = nw;
         }
         if (!accepted) return fail(c, JFNK_E_NOCONV, "line search failed");
+        psi_known = use_e;
+        psi_u = ph;
         std::swap(c->u, c->ut);
         std::swap(c->Au, c->Aut);
         std::swap(c->F, c->Ft);
