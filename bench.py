@@ -255,7 +255,7 @@ def main():
                 'share_of_step': round(ms / (sec32 * 1e3 * args.steps), 4)}
     kernel_shares = {k: {'launches': v[0], 'ms_total': round(v[1], 3),
                          'share': round(v[1] / (sec32 * 1e3 * args.steps), 4)} for k, v in shares.items()}
-    kernel_shares['arnoldi_cgs2'] = {'launches': arn_cnt, 'ms_total': round(arn_ms, 3),
+    kernel_shares['arnoldi_dcgs2'] = {'launches': arn_cnt, 'ms_total': round(arn_ms, 3),
                                      'share': round(arn_ms / (sec32 * 1e3 * args.steps), 4)}
     ge32 = reps32[-1]['ge_effective']
     log(f'FP32-MG: {sec32 * 1e3:.1f} ms/solve, {value:.3e} DoF/s, dominant {dom} {achieved:.0f} GB/s')

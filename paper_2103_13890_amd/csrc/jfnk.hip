@@ -25,9 +25,7 @@ constexpr int MAXR = 32;                  // restart cap (Gram-Schmidt slots)
 enum {
     S_FN2 = 0, S_FT2, S_ENER, S_BU, S_NUM64, S_ZN2, S_XN2, S_W2, S_EPS, S_SLOPE, S_DOT, S_RN2,
     S_COARSE = 16,          // 8 coarse statistics
-    S_H1 = 32,              // 32
-    S_H2 = 64,              // 32
-    S_SIG = 96,             // 32: inverse norms of the stored Krylov basis columns
+    S_COEF = 32,            // 96: Gram-Schmidt coefficients of one Krylov step
     S_LEV = 128,            // 16 per level
 };
 // per-level slots; L_PQ, L_PQB, L_PQC: rotating (Rayleigh quotient, ||q||^2)
@@ -595,15 +593,42 @@ jfnk_status fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, doubl
     vec_fill<double>(c->ex, x, n, 0.0);
     int total = 0;
     double est = rhs_norm;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
-    auto Hij = [&](int i, int j) -> double & { return H[i * m + j]; };
+    // Hr: the Hessenberg matrix as the Gram-Schmidt passes deliver it (column
+    // j is completed by the delayed reorthogonalisation of step j + 1); R, gv:
+    // its Givens QR and the rotated right-hand side, rebuilt every step
+    std::vector<double> Hr((m + 1) * m), R((m + 1) * m), gv(m + 1), y(m);
+    auto Hij = [&](int i, int j) -> double & { return Hr[i * m + j]; };
+    auto Rij = [&](int i, int j) -> double & { return R[i * m + j]; };
+    auto givens = [&](int ncol, double g0) {
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = g0;
+        std::vector<double> cs(ncol), sn(ncol);
+        for (int j = 0; j < ncol; ++j) {
+            for (int i = 0; i <= j + 1; ++i) Rij(i, j) = Hij(i, j);
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Rij(i, j) + sn[i] * Rij(i + 1, j);
+                Rij(i + 1, j) = -sn[i] * Rij(i, j) + cs[i] * Rij(i + 1, j);
+                Rij(i, j) = t;
+            }
+            const double rad = std::hypot(Rij(j, j), Rij(j + 1, j));
+            cs[j] = Rij(j, j) / rad;
+            sn[j] = Rij(j + 1, j) / rad;
+            Rij(j, j) = rad;
+            Rij(j + 1, j) = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+        }
+    };
     bool converged = false;
     for (int cycle = 0; cycle < c->opt.max_cycles && !converged; ++cycle) {
+        // the first candidate u_0 = the residual, unnormalised; its squared
+        // norm scales the first preconditioner input
         double beta;
+        const double *u0n2;
         if (cycle == 0) {
             beta = rhs_norm;
             if (beta <= tol) { converged = true; est = beta; break; }
-            vec_scale<double>(c->ex, g, nc, rhs, V, sign / beta, nullptr, nullptr);
+            vec_scale<double>(c->ex, g, nc, rhs, V, sign, nullptr, slot(c, S_RN2));
         } else {
             // r = sign*rhs - A x
             vec_dot<double, double>(c->ex, n, x, x, slot(c, S_XN2));
@@ -616,60 +641,60 @@ jfnk_status fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, doubl
             est = beta;
             if (!std::isfinite(beta)) return fail(c, JFNK_E_NONFINITE, "FGMRES: non-finite residual");
             if (beta <= tol) { converged = true; break; }
-            vec_scale<double>(c->ex, g, nc, V, V, 1.0 / beta, nullptr, nullptr);
         }
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = beta;
+        u0n2 = slot(c, S_RN2);
+        std::fill(Hr.begin(), Hr.end(), 0.0);
+        double g0 = beta;
         int k = 0;
-        // V_0 is normalised (sig_0 = 1); V_{j+1} is the orthogonalised w
-        // itself, its inverse norm sig_{j+1} written by the last pass
-        double *sig = slot(c, S_SIG);
-        vec_fill<double>(c->ex, sig, 1, 1.0);
         for (int j = 0; j < m; ++j) {
+            // z_j = M^-1 (u_j / ||u_j||), w = A z_j
             T *zj = Z + (size_t)j * n;
-            double *Vj1 = V + (size_t)(j + 1) * n;
-            precondition<T>(c, V + (size_t)j * n, j == 0 ? nullptr : slot(c, S_W2), zj);
+            precondition<T>(c, V + (size_t)j * n, j == 0 ? u0n2 : slot(c, S_W2), zj);
             CHK(apply_op<T>(c, op, zj, slot(c, S_ZN2), c->w));
             {
                 TimeScope ts(c, JFNK_TIMER_ARNOLDI, false);
-                arn_dots(c->ex, n, V, n, j + 1, sig, c->w, slot(c, S_H1));
-                arn_update(c->ex, n, V, n, j + 1, sig, slot(c, S_H1), c->w, c->w, slot(c, S_H2), nullptr);
-                arn_update(c->ex, n, V, n, j + 1, sig, slot(c, S_H2), c->w, Vj1, nullptr, slot(c, S_W2));
+                dcgs_dots(c->ex, n, V, n, j, c->w, slot(c, S_COEF));
+                dcgs_update(c->ex, n, V, n, j, slot(c, S_COEF), c->w, slot(c, S_W2));
             }
             CHK(check_launch(c));
-            double hh[2 * MAXR + 1];
-            HIPCHK(c, hipMemcpyAsync(hh, c->scal + S_H1, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c->st));
-            HIPCHK(c, hipMemcpyAsync(hh + MAXR, c->scal + S_H2, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, c->st));
-            HIPCHK(c, hipMemcpyAsync(hh + 2 * MAXR, c->scal + S_W2, sizeof(double), hipMemcpyDeviceToHost, c->st));
+            double hh[2 * MAXR + 4];
+            HIPCHK(c, hipMemcpyAsync(hh, c->scal + S_COEF, sizeof(double) * (2 * j + 3), hipMemcpyDeviceToHost, c->st));
+            HIPCHK(c, hipMemcpyAsync(hh + 2 * j + 3, c->scal + S_W2, sizeof(double), hipMemcpyDeviceToHost, c->st));
             HIPCHK(c, hipStreamSynchronize(c->st));
-            for (int i = 0; i <= j; ++i) Hij(i, j) = hh[i] + hh[MAXR + i];
-            Hij(j + 1, j) = std::sqrt(hh[2 * MAXR]);
-            if (!std::isfinite(Hij(j + 1, j))) return fail(c, JFNK_E_NONFINITE, "FGMRES: non-finite Arnoldi norm");
-            const bool breakdown = Hij(j + 1, j) == 0.0;
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
-                Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
-                Hij(i, j) = t;
+            const double *sj = hh, *bj = hh + j;
+            const double hjj = hh[2 * j + 1], rj = hh[2 * j + 2], un = std::sqrt(hh[2 * j + 3]);
+            if (!std::isfinite(rj) || !std::isfinite(un) || !std::isfinite(hjj))
+                return fail(c, JFNK_E_NONFINITE, "FGMRES: non-finite Arnoldi coefficients");
+            if (j == 0) {
+                g0 = rj;                                  // u_0 = r v_0
+            } else {
+                for (int i = 0; i < j; ++i) Hij(i, j - 1) += sj[i];   // delayed second projection
+                Hij(j, j - 1) = rj;
+                if (rj == 0.0) {                          // u_j lay in the span: column j - 1 ends the basis
+                    givens(j, g0);
+                    k = j;
+                    est = std::fabs(gv[j]);
+                    break;
+                }
             }
-            const double rad = std::hypot(Hij(j, j), Hij(j + 1, j));
-            cs[j] = Hij(j, j) / rad;
-            sn[j] = Hij(j + 1, j) / rad;
-            Hij(j, j) = rad;
-            Hij(j + 1, j) = 0.0;
-            gv[j + 1] = -sn[j] * gv[j];
-            gv[j] = cs[j] * gv[j];
+            // column j from the first projection of w; its last two entries
+            // are corrected by the next step, and are exact to rounding
+            // level (the once-projected norm) if the solve stops here
+            for (int i = 0; i < j; ++i) Hij(i, j) = bj[i];
+            Hij(j, j) = hjj;
+            Hij(j + 1, j) = un;
+            givens(j + 1, g0);
             k = j + 1;
             ++total;
             est = std::fabs(gv[j + 1]);
-            if (est <= tol || breakdown) break;
+            if (est <= tol || un == 0.0) break;
         }
         for (int i = k - 1; i >= 0; --i) {
             double acc = gv[i];
-            for (int j = i + 1; j < k; ++j) acc -= Hij(i, j) * y[j];
-            y[i] = acc / Hij(i, i);
+            for (int j = i + 1; j < k; ++j) acc -= Rij(i, j) * y[j];
+            y[i] = acc / Rij(i, i);
         }
-        arn_combine<T>(c->ex, n, Z, n, k, y.data(), x);
+        if (k > 0) arn_combine<T>(c->ex, n, Z, n, k, y.data(), x);
         CHK(check_launch(c));
         if (est <= tol) converged = true;
     }

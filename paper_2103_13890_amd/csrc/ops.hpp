@@ -145,16 +145,16 @@ template <typename T> void vec_exp(const Exec &, long long n, const double *m, T
 template <typename TA, typename TB>
 void vec_dot(const Exec &, long long n, const TA *x, const TB *y, double *out);
 
-// Arnoldi (CGS2) on FP64 basis vectors stored unnormalised: column j of the
-// orthonormal basis is sig_j V_j (V_j spaced by ld, sig_j a device slot).
-// h_j = sig_j V_j . w
-void arn_dots(const Exec &, long long n, const double *V, long long ld, int k, const double *sig, const double *w,
-              double *h);
-// wout = win - sum_j sig_j h_j V_j (wout may alias win); then
-// h2_j = sig_j V_j . wout (h2 non-null), or ||wout||^2 -> nrm2 and
-// 1/||wout|| -> sig_k (h2 null)
-void arn_update(const Exec &, long long n, const double *V, long long ld, int k, double *sig, const double *h,
-                const double *win, double *wout, double *h2, double *nrm2);
+// Arnoldi by classical Gram-Schmidt with delayed reorthogonalisation (DCGS2)
+// on FP64 columns spaced by ld: V_0..V_{J-1} final, V_J the candidate u
+// (projected once), w the new image.
+// dcgs_dots: coef[0..J) = V^T u, coef[J..2J) = V^T w, coef[2J] = 1/r,
+// coef[2J+1] = (u.w - s.b)/r, coef[2J+2] = r, with r = sqrt(u.u - s.s).
+void dcgs_dots(const Exec &, long long n, const double *V, long long ld, int J, const double *w, double *coef);
+// dcgs_update: V_J <- (u - V s)/r, V_{J+1} <- w - V b - coef[2J+1] V_J,
+// ||V_{J+1}||^2 -> nrm2
+void dcgs_update(const Exec &, long long n, double *V, long long ld, int J, const double *coef, const double *w,
+                 double *nrm2);
 // x += sum_j y_j Z_j (Z in TZ precision)
 template <typename TZ>
 void arn_combine(const Exec &, long long n, const TZ *Z, long long ld, int k, const double *y, double *x);

@@ -257,157 +257,173 @@ void vec_axpy(const Exec &ex, long long n, const double *x, double a, const doub
 }
 
 // ---- Gram-Schmidt passes ----------------------------------------------------------
-// The number of basis vectors K is a template parameter, so every load of a
-// pass is issued back to back (a run-time bound would put a branch, and a
-// wait, in front of each).  Up to 12 vectors a thread also takes two
-// elements per trip to keep more loads in flight.
+// Classical Gram-Schmidt with delayed reorthogonalisation (DCGS2: Swirydowicz,
+// Langou, Ananthan, Yang, Thomas, "Low synchronization Gram-Schmidt and
+// generalized minimal residual algorithms", Numer. Linear Algebra Appl. 2021;
+// Bielich et al., Parallel Computing 2022).  Iteration j holds the final
+// orthonormal columns V_0..V_{J-1} (J = j), the candidate u = column J,
+// projected once, and the new image w.  One reading pass forms
+//   a = V^T u,  b = V^T w,  c = u.u,  d = u.w;
+// then s = a (the delayed second projection of u), r = sqrt(c - s.s),
+// v_J = (u - V s) / r, and the coefficient of w on v_J is (d - s.b) / r.  One
+// update pass writes v_J over u and the next candidate
+//   u' = w - V b - ((d - s.b) / r) v_J
+// into column J + 1, with ||u'||^2.  In exact arithmetic this is CGS2 with
+// the second projection of each vector one iteration late; per iteration it
+// reads the basis twice instead of three times.
+// The number of basis vectors J is a template parameter, so the loads of a
+// pass issue back to back (the compiler places one wait in front of each
+// use); up to J = 12 a thread also takes two elements per trip.
 constexpr int ARN_MAX = 32;
 
-template <int K> struct ArnUnroll { static constexpr int U = K <= 12 ? 2 : 1; };
+template <int J> struct ArnUnroll { static constexpr int U = J <= 12 ? 2 : 1; };
 
-// h = V^T w
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_arn_dots(long long n, const double *V, long long ld, const double *w,
-                                                    Red red) {
-    constexpr int U = ArnUnroll<K>::U;
-    double s[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) s[j] = 0.0;
-    const long long stride = (long long)gridDim.x * BLOCK;
-    long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    for (; i + (U - 1) * stride < n; i += U * stride) {
-        double wi[U], vj[U][K];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            wi[u] = w[i + u * stride];
-#pragma unroll
-            for (int j = 0; j < K; ++j) vj[u][j] = V[j * ld + i + u * stride];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int j = 0; j < K; ++j) s[j] += vj[u][j] * wi[u];
-    }
-    if (U > 1 && i < n) {
-        const double wi = w[i];
-#pragma unroll
-        for (int j = 0; j < K; ++j) s[j] += V[j * ld + i] * wi;
-    }
-    block_partials<K>(s, red);
-}
-
-// wout = win - sum_j V_j (sig_j h_j); then h2 = V^T wout (H2) or ||wout||^2
-// (!H2) as partials.  The basis columns are stored unnormalised: column j is
-// sig_j V_j with sig_j its inverse norm, so a coefficient of the normalised
-// column is sig_j times one of the stored column.
-template <int K, bool H2>
-__global__ __launch_bounds__(BLOCK) void k_arn_update(long long n, const double *V, long long ld, const double *h,
-                                                      const double *sig, const double *win, double *wout,
-                                                      Red red) {
-    constexpr int U = ArnUnroll<K>::U;
-    constexpr int NS = H2 ? K : 1;
-    __shared__ double hs[K];
-    if (threadIdx.x < K) hs[threadIdx.x] = h[threadIdx.x] * sig[threadIdx.x];
-    __syncthreads();
-    double hj[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) hj[j] = hs[j];
+template <int J>
+__global__ __launch_bounds__(BLOCK) void k_dcgs_dots(long long n, const double *V, long long ld, const double *w,
+                                                     Red red) {
+    constexpr int U = ArnUnroll<J>::U;
+    constexpr int NS = 2 * J + 2;
+    const double *u = V + J * ld;
     double s[NS];
 #pragma unroll
-    for (int j = 0; j < NS; ++j) s[j] = 0.0;
-    auto finish_one = [&](long long idx, double a, const double *vj) {
+    for (int k = 0; k < NS; ++k) s[k] = 0.0;
+    auto acc = [&](double ui, double wi, const double *vk) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) a -= hj[j] * vj[j];
-        wout[idx] = a;
-        if constexpr (H2) {
-#pragma unroll
-            for (int j = 0; j < K; ++j) s[j] += vj[j] * a;
-        } else {
-            s[0] += a * a;
+        for (int k = 0; k < J; ++k) {
+            s[k] += vk[k] * ui;
+            s[J + k] += vk[k] * wi;
         }
+        s[2 * J] += ui * ui;
+        s[2 * J + 1] += ui * wi;
     };
     const long long stride = (long long)gridDim.x * BLOCK;
     long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
     for (; i + (U - 1) * stride < n; i += U * stride) {
-        double wi[U], vj[U][K];
+        double ui[U], wi[U], vk[U][J > 0 ? J : 1];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            wi[u] = win[i + u * stride];
+        for (int q = 0; q < U; ++q) {
+            ui[q] = u[i + q * stride];
+            wi[q] = w[i + q * stride];
 #pragma unroll
-            for (int j = 0; j < K; ++j) vj[u][j] = V[j * ld + i + u * stride];
+            for (int k = 0; k < J; ++k) vk[q][k] = V[k * ld + i + q * stride];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) finish_one(i + u * stride, wi[u], vj[u]);
+        for (int q = 0; q < U; ++q) acc(ui[q], wi[q], vk[q]);
     }
     if (U > 1 && i < n) {
-        double vj[K];
+        double vk[J > 0 ? J : 1];
 #pragma unroll
-        for (int j = 0; j < K; ++j) vj[j] = V[j * ld + i];
-        finish_one(i, win[i], vj);
+        for (int k = 0; k < J; ++k) vk[k] = V[k * ld + i];
+        acc(u[i], w[i], vk);
     }
     block_partials<NS>(s, red);
 }
 
-// h_j = sig_j t_j: dot products with the normalised columns
-struct FinScaleK {
+// coefficients of the update pass from the dot products t[0..2J+1]:
+// out[0..J) = s, out[J..2J) = b, out[2J] = 1/r, out[2J+1] = (d - s.b)/r,
+// out[2J+2] = r
+struct FinDcgs {
     double *out;
-    const double *sig;
-    int k;
+    int J;
     __device__ void operator()(const double *t) const {
-        for (int j = 0; j < k; ++j) out[j] = t[j] * sig[j];
+        double ss = 0.0, sb = 0.0;
+        for (int k = 0; k < J; ++k) {
+            out[k] = t[k];
+            out[J + k] = t[J + k];
+            ss += t[k] * t[k];
+            sb += t[k] * t[J + k];
+        }
+        const double rr = t[2 * J] - ss;
+        const double r = rr > 0.0 ? sqrt(rr) : 0.0;
+        const double ir = r > 0.0 ? 1.0 / r : 0.0;
+        out[2 * J] = ir;
+        out[2 * J + 1] = (t[2 * J + 1] - sb) * ir;
+        out[2 * J + 2] = r;
     }
 };
-// ||w||^2, and the inverse norm of w as the next column's sig
-struct FinNormSig {
-    double *out, *sig_next;
-    __device__ void operator()(const double *t) const {
-        out[0] = t[0];
-        sig_next[0] = t[0] > 0.0 ? 1.0 / sqrt(t[0]) : 0.0;
+
+template <int J>
+__global__ __launch_bounds__(BLOCK) void k_dcgs_update(long long n, double *V, long long ld, const double *coef,
+                                                       const double *w, Red red) {
+    constexpr int U = ArnUnroll<J>::U;
+    __shared__ double cs[2 * J + 2];
+    if (threadIdx.x < 2 * J + 2) cs[threadIdx.x] = coef[threadIdx.x];
+    __syncthreads();
+    double sk[J > 0 ? J : 1], bk[J > 0 ? J : 1];
+#pragma unroll
+    for (int k = 0; k < J; ++k) { sk[k] = cs[k]; bk[k] = cs[J + k]; }
+    const double ir = cs[2 * J], hj = cs[2 * J + 1];
+    double *u = V + J * ld, *un = V + (J + 1) * ld;
+    double nrm[1] = {0.0};
+    auto one = [&](long long idx, double ui, double wi, const double *vk) {
+#pragma unroll
+        for (int k = 0; k < J; ++k) {
+            ui -= sk[k] * vk[k];
+            wi -= bk[k] * vk[k];
+        }
+        const double vj = ui * ir;
+        u[idx] = vj;
+        const double x = wi - hj * vj;
+        un[idx] = x;
+        nrm[0] += x * x;
+    };
+    const long long stride = (long long)gridDim.x * BLOCK;
+    long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        double ui[U], wi[U], vk[U][J > 0 ? J : 1];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            ui[q] = u[i + q * stride];
+            wi[q] = w[i + q * stride];
+#pragma unroll
+            for (int k = 0; k < J; ++k) vk[q][k] = V[k * ld + i + q * stride];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) one(i + q * stride, ui[q], wi[q], vk[q]);
     }
-};
+    if (U > 1 && i < n) {
+        double vk[J > 0 ? J : 1];
+#pragma unroll
+        for (int k = 0; k < J; ++k) vk[k] = V[k * ld + i];
+        one(i, u[i], w[i], vk);
+    }
+    block_partials<1>(nrm, red);
+}
 
 static inline int arn_blocks(long long n) { return vblocks(n, 2048); }
 
-template <int K> void arn_dots_k(const Exec &ex, long long n, const double *V, long long ld, const double *sig,
-                                 const double *w, double *h) {
+template <int J> void dcgs_dots_k(const Exec &ex, long long n, const double *V, long long ld, const double *w,
+                                  double *coef) {
     const int nb = arn_blocks(n);
-    k_arn_dots<K><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, w, ex.red);
-    finish<K>(ex.st, ex.red, nb, FinScaleK{h, sig, K});
+    k_dcgs_dots<J><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, w, ex.red);
+    finish<2 * J + 2>(ex.st, ex.red, nb, FinDcgs{coef, J});
 }
-template <int K> void arn_update_k(const Exec &ex, long long n, const double *V, long long ld, double *sig,
-                                   const double *h, const double *win, double *wout, double *h2, double *nrm2) {
+template <int J> void dcgs_update_k(const Exec &ex, long long n, double *V, long long ld, const double *coef,
+                                    const double *w, double *nrm2) {
     const int nb = arn_blocks(n);
-    if (h2) {
-        k_arn_update<K, true><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, sig, win, wout, ex.red);
-        finish<K>(ex.st, ex.red, nb, FinScaleK{h2, sig, K});
-    } else {
-        k_arn_update<K, false><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, h, sig, win, wout, ex.red);
-        finish<1>(ex.st, ex.red, nb, FinNormSig{nrm2, sig + K});
-    }
+    k_dcgs_update<J><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, coef, w, ex.red);
+    finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 
-using DotsFn = void (*)(const Exec &, long long, const double *, long long, const double *, const double *,
-                        double *);
-using UpdFn = void (*)(const Exec &, long long, const double *, long long, double *, const double *,
-                       const double *, double *, double *, double *);
-template <int... Ks> constexpr std::array<DotsFn, sizeof...(Ks)> dots_table(std::integer_sequence<int, Ks...>) {
-    return {&arn_dots_k<Ks + 1>...};
+using DotsFn = void (*)(const Exec &, long long, const double *, long long, const double *, double *);
+using UpdFn = void (*)(const Exec &, long long, double *, long long, const double *, const double *, double *);
+template <int... Js> constexpr std::array<DotsFn, sizeof...(Js)> dots_table(std::integer_sequence<int, Js...>) {
+    return {&dcgs_dots_k<Js>...};
 }
-template <int... Ks> constexpr std::array<UpdFn, sizeof...(Ks)> upd_table(std::integer_sequence<int, Ks...>) {
-    return {&arn_update_k<Ks + 1>...};
+template <int... Js> constexpr std::array<UpdFn, sizeof...(Js)> upd_table(std::integer_sequence<int, Js...>) {
+    return {&dcgs_update_k<Js>...};
 }
-static constexpr auto kDots = dots_table(std::make_integer_sequence<int, ARN_MAX>{});
-static constexpr auto kUpd = upd_table(std::make_integer_sequence<int, ARN_MAX>{});
+static constexpr auto kDots = dots_table(std::make_integer_sequence<int, ARN_MAX - 1>{});
+static constexpr auto kUpd = upd_table(std::make_integer_sequence<int, ARN_MAX - 1>{});
 
-void arn_dots(const Exec &ex, long long n, const double *V, long long ld, int k, const double *sig, const double *w,
-              double *h) {
-    if (k < 1 || k > ARN_MAX) return;
-    kDots[k - 1](ex, n, V, ld, sig, w, h);
+void dcgs_dots(const Exec &ex, long long n, const double *V, long long ld, int J, const double *w, double *coef) {
+    if (J < 0 || J >= ARN_MAX - 1) return;
+    kDots[J](ex, n, V, ld, w, coef);
 }
-void arn_update(const Exec &ex, long long n, const double *V, long long ld, int k, double *sig, const double *h,
-                const double *win, double *wout, double *h2, double *nrm2) {
-    if (k < 1 || k > ARN_MAX) return;
-    kUpd[k - 1](ex, n, V, ld, sig, h, win, wout, h2, nrm2);
+void dcgs_update(const Exec &ex, long long n, double *V, long long ld, int J, const double *coef, const double *w,
+                 double *nrm2) {
+    if (J < 0 || J >= ARN_MAX - 1) return;
+    kUpd[J](ex, n, V, ld, coef, w, nrm2);
 }
 
 // x += Z y  (y passed by value)
