@@ -40,7 +40,8 @@ BYTES_PER_NODE = {
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STENCIL_SOURCES = ['common.hpp', 'elem.hpp', 'reduce.hpp', 'stencil.hpp', 'stencil_tiled.hpp', 'ops_stencil.inc']
+STENCIL_SOURCES = ['common.hpp', 'access.hpp', 'elem.hpp', 'reduce.hpp', 'stencil.hpp', 'stencil_tiled.hpp',
+                   'ops_stencil.inc']
 TRAFFIC_FILES = {'cheb_step_f32': 'cheb_step_f32_plap3d-256_hbm_traffic.md'}
 
 
