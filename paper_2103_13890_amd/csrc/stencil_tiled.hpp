@@ -27,11 +27,14 @@ namespace jfnk {
 
 // node rows per tile (register arrays), chosen by measurement at 256^3:
 // FP32 4 (under 128 VGPRs, 4 waves per SIMD; faster than 3, 5, 6 or 8
-// despite the larger y halo); FP64 6 for the plain FD quotient without
-// epilogue inputs (the outer J v; 8 spills registers), 4 otherwise.
+// despite the larger y halo); FP64: 4 for the plain FD quotient without
+// epilogue inputs (the outer J v: 166 VGPRs, 3 waves per SIMD, faster than
+// 6 rows at 2 waves), 3 for the residual (124 VGPRs, 4 waves per SIMD),
+// 4 otherwise.
 template <typename T, int MODE, class Epi> struct TileRows {
     static constexpr bool jv64 = sizeof(T) == 8 && MODE == M_FD_PLAIN && Epi::NIN == 0;
-    static constexpr int value = jv64 ? 6 : 4;
+    static constexpr bool res64 = sizeof(T) == 8 && MODE == M_RESID;
+    static constexpr int value = jv64 ? 4 : (res64 ? 3 : 4);
 };
 constexpr int TMAX_THREADS = 512;   // nx <= 512 elements per row
 
