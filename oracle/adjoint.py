@@ -24,7 +24,7 @@ def adjoint_solve(problem, finest, nlevels, u, m, rhs, mg_opts=None, rtol=1e-12,
     stats = stats or Stats()
     grids = make_grids(finest, nlevels)
     L = nlevels - 1
-    levels = mg_setup(problem, grids, u, m, mg_opts, None, stats)
+    levels = mg_setup(problem, grids, u, m, mg_opts, None, stats, {})
     rhs = _mask(finest, problem.ncomp, rhs)
 
     def A(lam):

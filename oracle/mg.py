@@ -27,6 +27,18 @@ V(nu1, nu2)-cycle).  Readings where the paper is silent or ambiguous:
   ||r|| <= max(atol, rtol ||r_coarse||) or maxit iterations (default: the
   number of coarse DoFs) and return lam_c = 0.  Shift loop of Algorithm 1
   with gamma = 5, capped at shift_max rounds.
+* Coarse L-BFGS preconditioner (CG-QN, Sec. 2 coarse level solver and
+  Sec. 3 setup, after Morales and Nocedal 2000), optional (coarse_qn = m
+  secant pairs; the paper's experiments use 20).  The first coarse CG of a
+  solve runs unpreconditioned and records every step's pair
+  s_k = alpha_k p_k, y_k = alpha_k (J - shift I) p_k.  Uniform sampling
+  over the t recorded steps keeps the pairs at steps floor(i t / m),
+  i = 0..m-1 (all of them when t <= m), of which those with s^T y > 0
+  form the preconditioner, oldest first.  It is applied by the two-loop
+  recursion with H_0 = (s^T y / y^T y) I of the newest kept pair, and
+  every later coarse CG of the solve (shifted ones included) is
+  preconditioned CG with it: same negative-curvature test p^T A_s p <= 0,
+  same Rayleigh quotient, same stop on the unpreconditioned residual.
 """
 from dataclasses import dataclass, field
 
@@ -53,6 +65,7 @@ class MGOptions:
     coarse_rtol: float = 1e-6
     shift_gamma: float = 5.0
     shift_max: int = 20
+    coarse_qn: int = 0               # L-BFGS secant pairs of the coarse CG (0: none)
     eps_mode: str = 'norm'           # 'norm' or 'paper'
     fd_root: float = np.sqrt(EPS64)  # sqrt of the machine epsilon
     seed: int = 0
@@ -68,6 +81,7 @@ class Level:
     lam: float = 0.0
     eig: np.ndarray = None
     power_iters: int = 0
+    qn: dict = None                  # coarse level: the solve's L-BFGS state
 
 
 @dataclass
@@ -165,8 +179,39 @@ def chebyshev(Jv, b, s, nu, lam, lo, hi, s_is_zero=False):
     return s
 
 
-def cg_shifted(Jv, b, s, shift, maxit, tol):
-    """CG on (J - shift I) s = b from s with the negative-curvature exit.
+def lbfgs_apply(pairs, r):
+    """H r for the L-BFGS inverse approximation of the pairs (s_i, y_i),
+    oldest first: the two-loop recursion with H_0 = (s^T y / y^T y) I of the
+    newest pair (Nocedal and Wright, Numerical Optimization, Alg. 7.4)."""
+    if not pairs:
+        return r.copy()
+    q = r.copy()
+    rho = [1.0 / float(np.sum(s * y)) for s, y in pairs]
+    a = [0.0] * len(pairs)
+    for i in range(len(pairs) - 1, -1, -1):
+        s, y = pairs[i]
+        a[i] = rho[i] * float(np.sum(s * q))
+        q = q - a[i] * y
+    s, y = pairs[-1]
+    z = (float(np.sum(s * y)) / float(np.sum(y * y))) * q
+    for i in range(len(pairs)):
+        s, y = pairs[i]
+        bi = rho[i] * float(np.sum(y * z))
+        z = z + (a[i] - bi) * s
+    return z
+
+
+def uniform_sample(t, m):
+    """Indices of the m steps kept out of t recorded ones (uniform sampling)."""
+    if t <= m:
+        return list(range(t))
+    return [(i * t) // m for i in range(m)]
+
+
+def cg_shifted(Jv, b, s, shift, maxit, tol, prec=None, record=None):
+    """CG on (J - shift I) s = b from s with the negative-curvature exit,
+    preconditioned by prec (a function r -> M^-1 r) when given; record, a
+    list, receives every step's pair (alpha p, alpha A_s p).
 
     Returns (s, lam_c, iterations): lam_c < 0 is the Rayleigh quotient of
     the shifted operator at the direction with non-positive curvature,
@@ -175,40 +220,58 @@ def cg_shifted(Jv, b, s, shift, maxit, tol):
     def As(v):
         return Jv(v) - shift * v
     r = b - As(s) if np.any(s) else b.copy()
-    p = r.copy()
-    rr = float(np.sum(r * r))
-    if np.sqrt(rr) <= tol:
+    if np.sqrt(float(np.sum(r * r))) <= tol:
         return s, 0.0, 0
+    z = prec(r) if prec is not None else r
+    p = z.copy()
+    rz = float(np.sum(r * z))
     for it in range(1, maxit + 1):
         q = As(p)
         pq = float(np.sum(p * q))
         if pq <= 0.0:
             return s, pq / float(np.sum(p * p)), it
-        alpha = rr / pq
+        alpha = rz / pq
+        if record is not None:
+            record.append((alpha * p, alpha * q))
         s = s + alpha * p
         r = r - alpha * q
-        rr_new = float(np.sum(r * r))
-        if np.sqrt(rr_new) <= tol:
+        if np.sqrt(float(np.sum(r * r))) <= tol:
             return s, 0.0, it
-        p = r + (rr_new / rr) * p
-        rr = rr_new
+        z = prec(r) if prec is not None else r
+        rz_new = float(np.sum(r * z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
     return s, 0.0, maxit
 
 
-def coarse_solve(Jv, r0, n_dof, opts, stats=None):
-    """The coarse branch of Algorithm 1: CG, then shifted CG while lam_c < 0."""
+def coarse_solve(Jv, r0, n_dof, opts, stats=None, qn=None):
+    """The coarse branch of Algorithm 1: CG, then shifted CG while lam_c < 0.
+    With opts.coarse_qn > 0 and a state dict qn: the first call records the
+    secant pairs, later ones (and this call's shifted rounds) precondition."""
     maxit = opts.coarse_maxit if opts.coarse_maxit > 0 else n_dof
     tol = max(opts.coarse_atol, opts.coarse_rtol * float(np.sqrt(np.sum(r0 * r0))))
+    use_qn = opts.coarse_qn > 0 and qn is not None
+    record = None
+    if use_qn and qn.get('pairs') is None:
+        record = []
+
+    def prec():
+        if use_qn and qn.get('pairs') is not None:
+            return lambda r: lbfgs_apply(qn['pairs'], r)
+        return None
     shift = 0.0
     s = np.zeros_like(r0)
-    s, lam_c, it = cg_shifted(Jv, r0, s, shift, maxit, tol)
+    s, lam_c, it = cg_shifted(Jv, r0, s, shift, maxit, tol, prec(), record)
+    if record is not None:
+        kept = [record[i] for i in uniform_sample(len(record), opts.coarse_qn)]
+        qn['pairs'] = [(sk, yk) for sk, yk in kept if float(np.sum(sk * yk)) > 0.0]
     iters = [it]
     rounds = 0
     while lam_c < 0.0 and rounds < opts.shift_max:
         if stats is not None:
             stats.neg_curv += 1
         shift = opts.shift_gamma * min(lam_c, shift)
-        s, lam_c, it = cg_shifted(Jv, r0, s, shift, maxit, tol)
+        s, lam_c, it = cg_shifted(Jv, r0, s, shift, maxit, tol, prec())
         iters.append(it)
         rounds += 1
     if stats is not None:
@@ -226,8 +289,9 @@ def make_grids(finest, nlevels):
     return g[::-1]
 
 
-def mg_setup(problem, grids, u, m, opts, prev_eigs=None, stats=None):
-    """Project the iterate (and coefficient), cache A_l(x_l), estimate lam_l."""
+def mg_setup(problem, grids, u, m, opts, prev_eigs=None, stats=None, qn=None):
+    """Project the iterate (and coefficient), cache A_l(x_l), estimate lam_l.
+    qn: the solve's coarse L-BFGS state (a dict kept across Newton steps)."""
     L = len(grids) - 1
     xs, ms = [None] * (L + 1), [None] * (L + 1)
     xs[L], ms[L] = u, m
@@ -243,6 +307,7 @@ def mg_setup(problem, grids, u, m, opts, prev_eigs=None, stats=None):
             stats.count(l)
         lev.eps_num = eps_numerator(grids[l], xs[l], opts)
         levels.append(lev)
+    levels[0].qn = qn
     for l in range(1, L + 1):
         lev = levels[l]
         v0 = prev_eigs[l] if prev_eigs is not None else random_start(lev.grid, problem.ncomp, opts.seed, l)
@@ -259,7 +324,7 @@ def vcycle(problem, levels, l, b, opts, stats=None):
     def Jv(v):
         return level_jv(problem, lev, v, stats, l)
     if l == 0:
-        s, _, _ = coarse_solve(Jv, b, lev.grid.n_dof(problem.ncomp), opts, stats)
+        s, _, _ = coarse_solve(Jv, b, lev.grid.n_dof(problem.ncomp), opts, stats, lev.qn)
         return s
     s = np.zeros_like(b)
     s = chebyshev(Jv, b, s, opts.nu_pre, lev.lam, opts.cheb_lo, opts.cheb_hi, s_is_zero=True)

@@ -122,6 +122,7 @@ def solve(problem, finest, nlevels, u0, b, m=None, mg_opts=None, opts=None, repo
     f0 = _norm(F)
     rep.fnorm.append(f0)
     eigs = None
+    qn = {}                                   # coarse L-BFGS pairs, built once per solve
     for k in range(opts.maxit + 1):
         fn = _norm(F)
         if not np.isfinite(fn):
@@ -132,7 +133,7 @@ def solve(problem, finest, nlevels, u0, b, m=None, mg_opts=None, opts=None, repo
             return u, rep
         if k == opts.maxit:
             break
-        levels = mg_setup(problem, grids, u, m, mg_opts, eigs, st)
+        levels = mg_setup(problem, grids, u, m, mg_opts, eigs, st, qn)
         eigs = [lev.eig for lev in levels]
         rep.lams.append([lev.lam for lev in levels])
         eta = min(0.5, fn / f0) if opts.forcing == 'relative' else min(0.5, fn)
