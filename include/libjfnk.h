@@ -132,6 +132,18 @@ typedef struct {
      * The difference form computes r_e(x + eps v) - r_e(x) per element
      * without subtracting two nearly equal vectors (see jfnk_jv). */
     int fd_form;
+    /* L-BFGS preconditioner of the coarse CG (CG-QN; Sec. 2, coarse level
+     * solver, and Sec. 3, setup): 0 plain CG; m in [1, 32] secant pairs (the
+     * paper uses 20).  The first coarse solve of a solve (jfnk_solve,
+     * jfnk_solve_steps, jfnk_adjoint_solve; after jfnk_create or
+     * mg_reset_eigvecs for the mg_* calls) runs plain CG and records every
+     * step's pair s = alpha p, y = alpha (J - shift I) p; the steps
+     * floor(i t / m), i < m, of its t steps (all of them if t <= m) with
+     * s.y > 0 are kept, oldest first.  Every later coarse CG of the solve is
+     * preconditioned by their two-loop recursion with H_0 = (s.y / y.y) I of
+     * the newest kept pair.  Needs a scalar kind whose coarse level has at
+     * most 1024 nodes (JFNK_E_INVAL otherwise). */
+    int coarse_qn;
 } jfnk_options;
 
 typedef struct {
@@ -150,6 +162,7 @@ typedef struct {
     int neg_curv;                        /* coarse negative-curvature exits */
     double last_shift;                   /* lambda_c+ of the last coarse solve */
     double time_ms;                      /* wall time of the solve (stream events) */
+    int coarse_qn_pairs;                 /* L-BFGS pairs kept (coarse_qn > 0), else 0 */
 } jfnk_report;
 
 typedef struct jfnk_ctx jfnk_ctx;
@@ -158,7 +171,8 @@ typedef struct jfnk_ctx jfnk_ctx;
 
 /* Defaults: nu 4/4, [0.06,1.2], power 30 / 1e-2, coarse rtol 1e-6, atol
  * 1e-12, gamma 5, restart 30 (at most JFNK_MAX_RESTART), Newton rtol 1e-8,
- * F64 levels, NORM step, RELATIVE forcing, AUTO merit, seed 0. */
+ * F64 levels, NORM step, RELATIVE forcing, AUTO merit, seed 0, plain coarse
+ * CG (coarse_qn 0). */
 void jfnk_default_options(jfnk_options *opt);
 
 /* Bytes of device workspace a context for (prob, opt) needs. */

@@ -29,8 +29,9 @@ Modules and the parts of the paper they follow:
                   P = 2^-d I^T (Sec. 2, transfer operators).
 * ``mg``          finite-difference Jacobian action (Sec. 1), power method
                   and Chebyshev smoother (Sec. 2, smoothers), shifted coarse
-                  CG with the negative-curvature exit (Sec. 2, coarse level
-                  solver) and the V-cycle (Algorithm 1).
+                  CG with the negative-curvature exit and its optional L-BFGS
+                  preconditioner (Sec. 2, coarse level solver) and the
+                  V-cycle (Algorithm 1).
 * ``krylov``      flexible GMRES(m) with two-pass classical Gram-Schmidt.
 * ``newton``      inexact Newton with cubic backtracking (Sec. 3, setup).
 * ``adjoint``     adjoint solve and the gradient of a misfit with respect

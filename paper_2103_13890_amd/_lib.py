@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
                 ('ls_maxit', ctypes.c_int), ('armijo', ctypes.c_double), ('vcycle_prec', ctypes.c_int),
                 ('eps_mode', ctypes.c_int), ('fd_root', ctypes.c_double), ('forcing', ctypes.c_int),
                 ('merit', ctypes.c_int), ('seed', ctypes.c_ulonglong), ('kernel_path', ctypes.c_int),
-                ('fd_form', ctypes.c_int)]
+                ('fd_form', ctypes.c_int), ('coarse_qn', ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -47,7 +47,8 @@ class Report(ctypes.Structure):
                 ('ge_level', ctypes.c_double * MAX_LEVELS), ('ge_effective', ctypes.c_double),
                 ('lambda_', ctypes.c_double * MAX_LEVELS), ('coarse_calls', ctypes.c_longlong),
                 ('coarse_iters', ctypes.c_longlong), ('neg_curv', ctypes.c_int),
-                ('last_shift', ctypes.c_double), ('time_ms', ctypes.c_double)]
+                ('last_shift', ctypes.c_double), ('time_ms', ctypes.c_double),
+                ('coarse_qn_pairs', ctypes.c_int)]
 
     def to_dict(self, nlevels):
         n = self.nhist
@@ -61,6 +62,7 @@ class Report(ctypes.Structure):
             'lambda': list(self.lambda_[:nlevels]), 'coarse_calls': self.coarse_calls,
             'coarse_iters': self.coarse_iters, 'neg_curv': self.neg_curv,
             'last_shift': self.last_shift, 'time_ms': self.time_ms,
+            'coarse_qn_pairs': self.coarse_qn_pairs,
         }
 
 

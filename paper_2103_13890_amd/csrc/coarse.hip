@@ -265,6 +265,39 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
     bool s_nonzero = false;
     T si = T(0), ri = T(0), pi = T(0), qi = T(0);
 
+    // L-BFGS preconditioner (CG-QN): the first solve with no pairs records
+    // every step of its first CG; pairs kept afterwards precondition all CG
+    // runs (two-loop recursion, H_0 = gamma I of the newest pair)
+    T *rec_s = (T *)ca.qn_rec, *rec_y = rec_s ? rec_s + (size_t)ca.qn_cap * nn : nullptr;
+    T *ps = (T *)ca.qn_pairs, *py = ps ? ps + (size_t)ca.qn_m * nn : nullptr;
+    // rho_k and the first-loop coefficients live in LDS (the same value in
+    // every lane); each lane touches only its own node's pair entries
+    __shared__ double srho[QN_MAX], sa[QN_MAX];
+    const bool qn_on = ca.qn_m > 0;
+    bool recording = qn_on && ca.qn_state[0] == 0.0;
+    int np = (qn_on && !recording) ? (int)ca.qn_state[1] : 0;
+    double gam = np > 0 ? ca.qn_state[2] : 1.0;
+    if (threadIdx.x < np) srho[threadIdx.x] = ca.qn_state[3 + threadIdx.x];
+    __syncthreads();
+    int nrec = 0;
+    auto prec = [&](T r) __attribute__((always_inline)) -> T {
+        if (np == 0) return r;
+        T q = r;
+        for (int k = np - 1; k >= 0; --k) {
+            const T sk = act ? ps[(size_t)k * nn + i] : T(0), yk = act ? py[(size_t)k * nn + i] : T(0);
+            const double ak = srho[k] * cg_bsum((double)sk * (double)q);
+            if (threadIdx.x == 0) sa[k] = ak;
+            q -= (T)ak * yk;
+        }
+        T z = (T)gam * q;
+        for (int k = 0; k < np; ++k) {
+            const T sk = act ? ps[(size_t)k * nn + i] : T(0), yk = act ? py[(size_t)k * nn + i] : T(0);
+            const double bk = srho[k] * cg_bsum((double)yk * (double)z);
+            z += (T)(sa[k] - bk) * sk;
+        }
+        return z;
+    };
+
     auto cg = [&](double shift) __attribute__((always_inline)) -> double {
         if (s_nonzero) {
             const double ss = cg_bsum((double)si * (double)si);
@@ -274,33 +307,86 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
         } else {
             ri = bi;
         }
-        pi = ri;
         double rr = cg_bsum((double)ri * (double)ri);
         if (sqrt(rr) <= tol) return 0.0;
-        double pp = rr;
+        T zi = prec(ri);
+        pi = zi;
+        double rz = np > 0 ? cg_bsum((double)ri * (double)zi) : rr;
+        double pp = np > 0 ? cg_bsum((double)pi * (double)pi) : rr;
         for (int it = 1; it <= ca.maxit; ++it) {
             qi = apply(pi, pp, shift);
             ++fd;
             ++iters;
             const double pq = cg_bsum((double)pi * (double)qi);
             if (pq <= 0.0) return pq / pp;
-            const double alpha = rr / pq;
+            const double alpha = rz / pq;
             const T a = (T)alpha;
+            if (recording && nrec < ca.qn_cap) {
+                if (act) {
+                    rec_s[(size_t)nrec * nn + i] = a * pi;
+                    rec_y[(size_t)nrec * nn + i] = a * qi;
+                }
+                ++nrec;
+            }
             si += a * pi;
             ri -= a * qi;
             s_nonzero = true;
             const double rn = cg_bsum((double)ri * (double)ri);
             if (sqrt(rn) <= tol) return 0.0;
-            const T beta = (T)(rn / rr);
-            pi = ri + beta * pi;
+            zi = prec(ri);
+            const double rzn = np > 0 ? cg_bsum((double)ri * (double)zi) : rn;
+            const T beta = (T)(rzn / rz);
+            pi = zi + beta * pi;
             pp = cg_bsum((double)pi * (double)pi);
-            rr = rn;
+            rz = rzn;
         }
         return 0.0;
     };
 
+    // after the recording CG: keep the uniform sample floor(k t / m) with
+    // positive curvature, oldest first; rho_k and gamma to the state
+    auto keep_pairs = [&]() __attribute__((always_inline)) {
+        const int t = nrec, m = ca.qn_m;
+        const int nsel = t <= m ? t : m;
+        int kept = 0;
+        double g_s = 0.0;
+        for (int k = 0; k < nsel; ++k) {
+            const int src = t <= m ? k : (int)(((long long)k * t) / m);
+            const T sk = act ? rec_s[(size_t)src * nn + i] : T(0), yk = act ? rec_y[(size_t)src * nn + i] : T(0);
+            const double sy = cg_bsum((double)sk * (double)yk);
+            if (sy > 0.0) {
+                const double yy = cg_bsum((double)yk * (double)yk);
+                if (act) {
+                    ps[(size_t)kept * nn + i] = sk;
+                    py[(size_t)kept * nn + i] = yk;
+                }
+                if (threadIdx.x == 0) {
+                    ca.qn_state[3 + kept] = 1.0 / sy;
+                    srho[kept] = 1.0 / sy;
+                }
+                g_s = sy / yy;
+                ++kept;
+            }
+        }
+        if (threadIdx.x == 0) {
+            ca.qn_state[0] = 1.0;
+            ca.qn_state[1] = (double)kept;
+            ca.qn_state[2] = kept > 0 ? g_s : 1.0;
+        }
+        // the pairs written above are read back by other lanes in prec()
+        __threadfence_block();
+        __syncthreads();
+        np = kept;
+        gam = kept > 0 ? g_s : 1.0;
+        recording = false;
+    };
+
     double shift = 0.0;
     double lam_c = cg(shift);
+    if (recording) {
+        __syncthreads();
+        keep_pairs();
+    }
     int rounds = 0;
     int negc = lam_c < 0.0 ? 1 : 0;
     while (lam_c < 0.0 && rounds < ca.shift_max) {
@@ -320,13 +406,20 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
     }
 }
 
+static size_t coarse_small_lds(const Grid &g, int kind, size_t eb) {
+    const long long ne = (long long)g.nx * g.ny * (g.dim == 3 ? g.nz : 1);
+    return (size_t)((kind == JFNK_INVCOEF ? 3 : 2) * g.nn + (g.dim == 3 ? 8 : 4) * ne) * eb;
+}
+bool coarse_small(const Grid &g, int kind, size_t eb) {
+    return kind != JFNK_NEOHOOKE && g.nn <= CBLOCK && coarse_small_lds(g, kind, eb) <= 64 * 1024;
+}
+
 template <int DIM, int KIND, typename T>
 static void launch_coarse(const Exec &ex, int mode, const Grid &g, const Phys &ph, const T *kap, const T *x,
                           const T *Ax, const double *num, const T *b, T *s, T *work, const CoarseArgs &ca) {
     if constexpr (KIND != JFNK_NEOHOOKE) {
-        const long long ne = (long long)g.nx * g.ny * (DIM == 3 ? g.nz : 1);
-        const size_t lds = (size_t)((KIND == JFNK_INVCOEF ? 3 : 2) * g.nn + Cell<DIM>::NV * ne) * sizeof(T);
-        if (g.nn <= CBLOCK && lds <= 64 * 1024) {
+        const size_t lds = coarse_small_lds(g, KIND, sizeof(T));
+        if (coarse_small(g, KIND, sizeof(T))) {
             if (mode == M_FD_DIFF)
                 k_coarse_small<DIM, KIND, M_FD_DIFF, T><<<1, CBLOCK, lds, ex.st>>>(g, ph, kap, x, Ax, num, b, s, ca);
             else

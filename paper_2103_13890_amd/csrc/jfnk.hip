@@ -69,6 +69,10 @@ struct jfnk_ctx {
     std::string err;
     TimerRec timers[JFNK_TIMER_COUNT];
     hipEvent_t t0 = nullptr, t1 = nullptr;
+    // coarse L-BFGS preconditioner (CG-QN): recorded steps, kept pairs, state
+    void *qn_rec = nullptr, *qn_pairs = nullptr;
+    double *qn_state = nullptr;
+    int qn_cap = 0;
     // pinned host copies of the power method's slot pairs, one event each
     double *hpin = nullptr;
     hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
@@ -142,6 +146,9 @@ std::string validate(const jfnk_problem *p, const jfnk_options *o) {
     if (p->kind == JFNK_NEOHOOKE && !(p->param[0] > 0.0 && p->param[1] > -1.0 && p->param[1] < 0.5))
         return "NEOHOOKE needs E > 0 and -1 < nu < 0.5";
     if (o->restart < 1 || o->restart > MAXR - 1) return "restart must be in [1, 31]";
+    if (o->coarse_qn < 0 || o->coarse_qn > QN_MAX) return "coarse_qn must be in [0, 32]";
+    if (o->coarse_qn > 0 && !coarse_small(level_grid(*p, 0), p->kind, esize(o->vcycle_prec)))
+        return "coarse_qn needs a scalar kind with at most 1024 coarse nodes";
     if (o->nu_pre < 0 || o->nu_post < 0) return "smoothing degrees must be >= 0";
     if (o->vcycle_prec != JFNK_F32 && o->vcycle_prec != JFNK_F64) return "vcycle_prec must be F32 or F64";
     if (o->eps_mode != JFNK_EPS_NORM && o->eps_mode != JFNK_EPS_PAPER) return "unknown eps_mode";
@@ -190,6 +197,14 @@ void plan(jfnk_ctx *c, Carve &cv) {
         L.q = cv.take(vb);
         // coarse solver: r, p, q and the per-element contributions (8 per element)
         L.cw = l == 0 ? cv.take(11 * vb) : nullptr;
+    }
+    if (c->opt.coarse_qn > 0) {
+        const Grid &g0 = c->lev[0].g;
+        const size_t vb0 = (size_t)g0.nn * nc * es;
+        c->qn_cap = c->opt.coarse_maxit > 0 ? c->opt.coarse_maxit : (int)level_dofs(g0, nc);
+        c->qn_rec = cv.take(2 * (size_t)c->qn_cap * vb0);
+        c->qn_pairs = cv.take(2 * (size_t)c->opt.coarse_qn * vb0);
+        c->qn_state = (double *)cv.take(64 * sizeof(double));
     }
     const Grid gf = level_grid(c->prob, c->prob.nlevels - 1);
     c->nn = gf.nn;
@@ -527,6 +542,13 @@ void vcycle(jfnk_ctx *c, int l, const T *b, T *s_out, double *s_out_n2, const do
         ca.rtol = c->opt.coarse_rtol;
         ca.gamma = c->opt.shift_gamma;
         ca.stats = slot(c, S_COARSE);
+        if (c->opt.coarse_qn > 0) {
+            ca.qn_m = c->opt.coarse_qn;
+            ca.qn_cap = c->qn_cap;
+            ca.qn_rec = c->qn_rec;
+            ca.qn_pairs = c->qn_pairs;
+            ca.qn_state = c->qn_state;
+        }
         coarse_solve<T>(c->ex, mg_mode(c), L.g, c->ph, CP<T>(L.kap), CP<T>(L.x), CP<T>(L.Ax), lslot(c, 0, L_NUM), b, s_out,
                         P<T>(L.cw), ca);
         if (s_out_n2) vec_dot<T, T>(c->ex, L.g.nn * nc, s_out, s_out, s_out_n2);
@@ -736,6 +758,11 @@ jfnk_status merit_energy(jfnk_ctx *c, const double *s, double *psi) {
     return JFNK_OK;
 }
 
+// forget the coarse L-BFGS pairs: the next coarse solve records new ones
+void qn_reset(jfnk_ctx *c) {
+    if (c->opt.coarse_qn > 0) vec_fill<double>(c->ex, c->qn_state, 3, 0.0);
+}
+
 void report_init(jfnk_ctx *c, jfnk_report *rep) {
     std::memset(rep, 0, sizeof(*rep));
     for (int l = 0; l < JFNK_MAX_LEVELS; ++l) c->ge[l] = 0.0;
@@ -757,6 +784,12 @@ void report_finish(jfnk_ctx *c, jfnk_report *rep) {
         eff += std::ldexp(c->ge[l], -c->prob.dim * (c->L - l));
     }
     rep->ge_effective = eff;
+    if (c->opt.coarse_qn > 0) {
+        double st[2] = {0.0, 0.0};
+        if (hipMemcpyAsync(st, c->qn_state, sizeof(st), hipMemcpyDeviceToHost, c->st) == hipSuccess &&
+            hipStreamSynchronize(c->st) == hipSuccess)
+            rep->coarse_qn_pairs = st[0] != 0.0 ? (int)st[1] : 0;
+    }
 }
 
 double line_cubic(double alpha, double ph, double phi0, double slope, bool have_prev, double ap, double pp) {
@@ -975,6 +1008,10 @@ jfnk_status jfnk_create(const jfnk_problem *p, const jfnk_options *o, void *ws, 
     hipError_t e = hipHostMalloc((void **)&c->hpin, 8 * sizeof(double), hipHostMallocDefault);
     for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&c->pev[k], hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemsetAsync(c->scal, 0, NSLOT * sizeof(double), c->st);
+    if (e == hipSuccess) {
+        qn_reset(c);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
         g_err = std::string("jfnk_create: ") + hipGetErrorString(e);
@@ -1137,6 +1174,8 @@ jfnk_status mg_setup(jfnk_ctx *c, const double *u, const double *coef) {
 jfnk_status mg_reset_eigvecs(jfnk_ctx *c) {
     if (!c) return fail(nullptr, JFNK_E_INVAL, "null context");
     c->have_eigs = false;
+    qn_reset(c);
+    CHK(check_launch(c));
     return JFNK_OK;
 }
 
@@ -1211,8 +1250,9 @@ jfnk_status mg_vcycle(jfnk_ctx *c, const double *b, double *s) {
 // One Newton solve with load scale * b from u; u receives the last
 // accepted iterate when write_back or on success.
 static jfnk_status solve_once(jfnk_ctx *c, double *u, const double *coef, const double *b, double scale,
-                              jfnk_report *rep, bool write_back) {
+                              jfnk_report *rep, bool write_back, bool first) {
     report_init(c, rep);
+    if (first) qn_reset(c);
     HIPCHK(c, hipMemsetAsync(c->scal + S_COARSE, 0, 8 * sizeof(double), c->st));
     if (!c->t0) {
         HIPCHK(c, hipEventCreate(&c->t0));
@@ -1247,7 +1287,7 @@ jfnk_status jfnk_solve(jfnk_ctx *c, double *u, const double *coef, const double 
     if (c->prob.kind == JFNK_INVCOEF && !coef) return fail(c, JFNK_E_INVAL, "INVCOEF needs coef");
     jfnk_report local;
     if (!rep) rep = &local;
-    return solve_once(c, u, coef, b, 1.0, rep, true);
+    return solve_once(c, u, coef, b, 1.0, rep, true, true);
 }
 
 jfnk_status jfnk_solve_steps(jfnk_ctx *c, double *u, const double *coef, const double *b, int nsteps,
@@ -1265,7 +1305,7 @@ jfnk_status jfnk_solve_steps(jfnk_ctx *c, double *u, const double *coef, const d
     while (t < 1.0 - 1e-12) {
         const double step = std::min(dt, 1.0 - t);
         const double target = t + step >= 1.0 - 1e-12 ? 1.0 : t + step;   // the full load exactly
-        last = solve_once(c, u, coef, b, target, &one, false);
+        last = solve_once(c, u, coef, b, target, &one, false, first);
         if (last == JFNK_E_DEVICE || last == JFNK_E_INVAL) return last;
         if (first) rep->fnorm0 = one.fnorm0;
         first = false;
@@ -1273,6 +1313,7 @@ jfnk_status jfnk_solve_steps(jfnk_ctx *c, double *u, const double *coef, const d
         rep->linear_iters += one.linear_iters;
         rep->coarse_calls += one.coarse_calls;
         rep->coarse_iters += one.coarse_iters;
+        rep->coarse_qn_pairs = one.coarse_qn_pairs;
         rep->neg_curv += one.neg_curv;
         rep->ge_effective += one.ge_effective;
         for (int l = 0; l < JFNK_MAX_LEVELS; ++l) {
@@ -1322,6 +1363,7 @@ jfnk_status jfnk_adjoint_solve(jfnk_ctx *c, const double *u, const double *coef,
     jfnk_report local;
     if (!rep) rep = &local;
     report_init(c, rep);
+    qn_reset(c);
     HIPCHK(c, hipMemsetAsync(c->scal + S_COARSE, 0, 8 * sizeof(double), c->st));
     const Grid &g = c->lev[c->L].g;
     HIPCHK(c, hipMemcpyAsync(c->u, u, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->st));

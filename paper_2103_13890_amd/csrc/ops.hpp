@@ -171,12 +171,23 @@ void tr_prolong_add(const Exec &, const Grid &fine, const Grid &coarse, int nc, 
                     double *nrm2);
 
 // ---- coarse solve (Algorithm 1, level 0) ------------------------------------------
+constexpr int QN_MAX = 32;   // secant pairs of the coarse L-BFGS preconditioner
 struct CoarseArgs {
     int maxit, shift_max;
     double atol, rtol, gamma;
     double *stats;      // [0] last shift, [1] total CG iterations, [2] rounds, [3] FD evaluations,
                         // [4] negative-curvature exits (accumulated over calls)
+    // L-BFGS preconditioner (CG-QN), qn_m > 0 pairs: the first call records
+    // every CG step's pair into qn_rec ([2][qn_cap][nn], level precision)
+    // and keeps a uniform sample in qn_pairs ([2][qn_m][nn]); qn_state:
+    // [0] 0 none / 1 built, [1] pairs kept, [2] gamma, [3 + i] 1/(s_i.y_i)
+    int qn_m = 0, qn_cap = 0;
+    void *qn_rec = nullptr, *qn_pairs = nullptr;
+    double *qn_state = nullptr;
 };
+// whether the coarse solve of this level runs in the one-workgroup kernel
+// that keeps the level in LDS (the one that supports the L-BFGS preconditioner)
+bool coarse_small(const Grid &, int kind, size_t elem_bytes);
 template <typename T>
 void coarse_solve(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
                   const double *num, const T *b, T *s, T *work, const CoarseArgs &);
