@@ -11,8 +11,14 @@ flexible GMRES (Saad, SIAM J. Sci. Comput. 14, 1993) with restart m = 30:
     Givens rotations on the Hessenberg matrix; |g_{j+1}| is ||b - A x_j||
     x = x + Z y after the cycle, restart while the estimate exceeds tol.
 
+The paper's own outer solver, CG with the multigrid preconditioner
+(Sec. 3, setup), is ``pcg``: preconditioned conjugate gradients in the
+Hestenes-Stiefel form from x = 0, stopped when the recursive residual
+reaches tol, or at a direction of non-positive curvature.
+
 Pins: on small dense systems the result matches numpy.linalg.solve, and
-the estimate matches the true residual (tests/test_oracle_krylov.py).
+the estimate matches the true residual; PCG with the identity is plain CG,
+with the exact inverse it takes one step (tests/test_oracle_krylov.py).
 """
 import numpy as np
 
@@ -75,3 +81,34 @@ def fgmres(A, b, M, tol, restart=30, max_cycles=50, x0=None):
         if est <= tol:
             return x, total, est, True
     return x, total, est, False
+
+
+def pcg(A, b, M, tol, maxit):
+    """Preconditioned CG on A x = b from x = 0 to ||r|| <= tol (recursive
+    residual), M(r) the preconditioner.  Returns (x, iterations, ||r||, ok);
+    ok is False at non-positive curvature p^T A p <= 0 or after maxit steps
+    (x is then the last iterate)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    rn = np.sqrt(_dot(r, r))
+    if rn <= tol:
+        return x, 0, rn, True
+    z = M(r)
+    p = z.copy()
+    rz = _dot(r, z)
+    for it in range(1, maxit + 1):
+        q = A(p)
+        pq = _dot(p, q)
+        if pq <= 0.0:
+            return x, it, rn, False
+        alpha = rz / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rn = np.sqrt(_dot(r, r))
+        if rn <= tol:
+            return x, it, rn, True
+        z = M(r)
+        rz_new = _dot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, maxit, rn, False

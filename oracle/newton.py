@@ -19,7 +19,9 @@ multigrid-preconditioned Krylov solve.  Readings:
   backtrack quadratic, later ones cubic through the two latest trials,
   each new step kept in [0.1, 0.5] times the previous; a non-finite merit
   halves alpha.
-* outer solver: flexible GMRES(30), preconditioned by one V-cycle.
+* outer solver: flexible GMRES(30), preconditioned by one V-cycle
+  ('fgmres', default), or the paper's CG with the V-cycle as preconditioner
+  ('cg', at most restart * max_cycles steps).
 * outer J v: the finite-difference quotient on the finest level at the
   Newton iterate, the same operator the finest smoother uses.
 
@@ -31,7 +33,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .krylov import fgmres
+from .krylov import fgmres, pcg
 from .mg import MGOptions, Stats, level_jv, make_grids, mg_setup, vcycle
 from .problems import _mask, apply_A, energy
 
@@ -49,6 +51,7 @@ class NewtonOptions:
     ls_maxit: int = 30
     armijo: float = 1e-4
     merit: str = 'auto'              # 'auto': energy if variational; 'residual'
+    outer: str = 'fgmres'            # 'fgmres' or 'cg'
 
 
 @dataclass
@@ -144,7 +147,10 @@ def solve(problem, finest, nlevels, u0, b, m=None, mg_opts=None, opts=None, repo
 
         def M(v):
             return vcycle(problem, levels, L, v, mg_opts, st)
-        dx, its, _, _ = fgmres(A, -F, M, eta * fn, opts.restart, opts.max_cycles)
+        if opts.outer == 'cg':
+            dx, its, _, _ = pcg(A, -F, M, eta * fn, opts.restart * opts.max_cycles)
+        else:
+            dx, its, _, _ = fgmres(A, -F, M, eta * fn, opts.restart, opts.max_cycles)
         rep.linear_iters += its
         rep.lin.append(its)
         rep.eta.append(eta)

@@ -1,7 +1,8 @@
-"""Pins of the oracle's flexible GMRES against dense linear algebra."""
+"""Pins of the oracle's flexible GMRES and preconditioned CG against dense
+linear algebra; CG also against its finite termination on an SPD system."""
 import numpy as np
 
-from oracle.krylov import fgmres
+from oracle.krylov import fgmres, pcg
 
 
 def _system(n, seed):
@@ -43,3 +44,39 @@ def test_fgmres_happy_breakdown():
 def test_fgmres_zero_rhs():
     x, its, est, ok = fgmres(lambda v: v, np.zeros(5), lambda v: v, 0.0)
     assert ok and its == 0 and not np.any(x)
+
+
+def _spd(n, seed, cond):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    return (Q * np.geomspace(1.0, cond, n)) @ Q.T, rng.normal(size=n)
+
+
+def test_pcg_matches_dense_solve():
+    A, b = _spd(50, 2, 1e3)
+    D = np.diag(A)
+    x, its, rn, ok = pcg(lambda v: A @ v, b, lambda v: v / D, 1e-12 * np.linalg.norm(b), 500)
+    assert ok
+    ref = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - ref) < 1e-9 * np.linalg.norm(ref)
+    # the recursive residual tracks the true one
+    assert abs(np.linalg.norm(b - A @ x) - rn) < 1e-10 * np.linalg.norm(b)
+
+
+def test_pcg_finite_termination_and_exact_preconditioner():
+    # 6 distinct eigenvalues: unpreconditioned CG ends in at most 6 steps
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.normal(size=(30, 30)))
+    A = (Q * np.repeat([1.0, 2.0, 3.0, 5.0, 8.0, 13.0], 5)) @ Q.T
+    b = rng.normal(size=30)
+    x, its, rn, ok = pcg(lambda v: A @ v, b, lambda v: v, 1e-10 * np.linalg.norm(b), 100)
+    assert ok and its <= 6
+    x, its, rn, ok = pcg(lambda v: A @ v, b, lambda v: np.linalg.solve(A, v), 1e-10 * np.linalg.norm(b), 100)
+    assert ok and its == 1
+
+
+def test_pcg_negative_curvature_stop():
+    A = np.diag([2.0, -1.0, 3.0])
+    b = np.array([0.0, 1.0, 0.0])
+    x, its, rn, ok = pcg(lambda v: A @ v, b, lambda v: v, 1e-12, 10)
+    assert not ok and its == 1 and not np.any(x)
