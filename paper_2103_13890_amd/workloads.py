@@ -19,6 +19,13 @@ Workloads (all synthetic; the paper uses analytic PDEs, no datasets):
 * invcoef3d-128   -div(e^m (1 + u^2) grad u) = f on 128^3, m a Matern-like
                   field (sigma 0.5, length 0.1, seed 3), u_obs from a second
                   field (seed 4), 5 levels
+* bratu2d-800     the paper's Bratu experiment on Q1 elements: lam = 5, a
+                  25 x 25 coarse mesh refined five times (800 x 800, 6
+                  levels), solved with the paper's settings (PAPER_OPTIONS)
+* minsurf2d-800   the paper's minimal-surface experiment on the same
+                  hierarchy: the p-Laplacian energy with p = 1, delta = 1 is
+                  int sqrt(1 + |grad u|^2); u = 0 on x = 0, 1 and u = x(1 - x)
+                  on y = 0, 1; paper settings
 """
 import numpy as np
 
@@ -111,7 +118,31 @@ def normal_vector(n, faces, seed, ncomp=1):
     return v
 
 
+def dirichlet_state(w):
+    """Start state of a preset: its Dirichlet data on the boundary nodes, 0 elsewhere.
+
+    'minsurf': u = x(1 - x) on the faces y = 0 and y = 1, 0 on x = 0 and x = 1
+    (Sec. 3, minimal surface); presets without boundary data start from 0.
+    """
+    n, h = w['n'], w['h']
+    shape = node_shape(n)
+    u = np.zeros(shape) if w['kind'] != 'neohooke' else np.zeros((3,) + shape)
+    if w.get('dirichlet_data') == 'minsurf':
+        x = np.arange(n[0] + 1) * h
+        u[0, :] = x * (1.0 - x)
+        u[-1, :] = x * (1.0 - x)
+    return u
+
+
 # ---- presets --------------------------------------------------------------------------
+# The paper's solver settings (Sec. 3, setup): CG-MG outer solver, V(5, 5)
+# cycles, power method <= 30 iterations or 1e-2 change, the paper's FD step,
+# coarse CG-QN with 20 pairs and shift gamma = 5 stopped at ||r|| <= 1e-12,
+# forcing min(0.5, ||F||), stop at ||F|| <= 1e-6, FP64 levels.
+PAPER_OPTIONS = dict(nu_pre=5, nu_post=5, power_maxit=30, power_rtol=1e-2, eps_mode=1, coarse_atol=1e-12,
+                     coarse_rtol=0.0, coarse_qn=20, shift_gamma=5.0, outer_krylov=1, forcing=1,
+                     newton_rtol=0.0, newton_atol=1e-6, vcycle_prec=0)
+
 WORKLOADS = {
     'bratu2d-32': dict(kind='bratu', n=(32, 32), h=1 / 32, faces=ALL2, params=(5.0,), nlevels=3,
                        options=dict(nu_pre=3, nu_post=3, power_fixed=1, power_maxit=10, vcycle_prec=0,
@@ -126,6 +157,10 @@ WORKLOADS = {
     'invcoef3d-128': dict(kind='invcoef', n=(128, 128, 128), h=1 / 128, faces=ALL3, params=(), nlevels=5,
                           load_seed=1, m_seed=3, obs_seed=4,
                           options=dict(nu_pre=4, nu_post=4, vcycle_prec=0, coarse_rtol=1e-6)),
+    'bratu2d-800': dict(kind='bratu', n=(800, 800), h=1 / 800, faces=ALL2, params=(5.0,), nlevels=6,
+                        options=dict(PAPER_OPTIONS)),
+    'minsurf2d-800': dict(kind='plap', n=(800, 800), h=1 / 800, faces=ALL2, params=(1.0, 1.0), nlevels=6,
+                          dirichlet_data='minsurf', options=dict(PAPER_OPTIONS)),
 }
 
 
