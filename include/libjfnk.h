@@ -81,6 +81,9 @@ typedef enum { JFNK_FORCING_RELATIVE = 0, JFNK_FORCING_PAPER = 1 } jfnk_forcing;
  * otherwise; RESIDUAL = always 1/2||F||^2. */
 typedef enum { JFNK_MERIT_AUTO = 0, JFNK_MERIT_RESIDUAL = 1 } jfnk_merit;
 
+/* Outer Krylov solver of the Newton step (jfnk_options.outer_krylov). */
+typedef enum { JFNK_OUTER_FGMRES = 0, JFNK_OUTER_CG = 1 } jfnk_outer;
+
 #define JFNK_FACE_XLO 1u
 #define JFNK_FACE_XHI 2u
 #define JFNK_FACE_YLO 4u
@@ -141,9 +144,16 @@ typedef struct {
      * floor(i t / m), i < m, of its t steps (all of them if t <= m) with
      * s.y > 0 are kept, oldest first.  Every later coarse CG of the solve is
      * preconditioned by their two-loop recursion with H_0 = (s.y / y.y) I of
-     * the newest kept pair.  Needs a scalar kind whose coarse level has at
-     * most 1024 nodes (JFNK_E_INVAL otherwise). */
+     * the newest kept pair. */
     int coarse_qn;
+    /* Krylov solver of the Newton step J dx = -F (Sec. 3, setup):
+     * JFNK_OUTER_FGMRES flexible GMRES(restart), right-preconditioned by one
+     * V-cycle per step; JFNK_OUTER_CG the paper's CG-MG: conjugate gradients
+     * preconditioned by one V-cycle per step, at most restart * max_cycles
+     * steps, stopped at ||r|| <= eta ||F|| or at a direction p with
+     * p.Jp <= 0 (the step so far is kept).  jfnk_adjoint_solve always uses
+     * FGMRES. */
+    int outer_krylov;
 } jfnk_options;
 
 typedef struct {
@@ -172,7 +182,7 @@ typedef struct jfnk_ctx jfnk_ctx;
 /* Defaults: nu 4/4, [0.06,1.2], power 30 / 1e-2, coarse rtol 1e-6, atol
  * 1e-12, gamma 5, restart 30 (at most JFNK_MAX_RESTART), Newton rtol 1e-8,
  * F64 levels, NORM step, RELATIVE forcing, AUTO merit, seed 0, plain coarse
- * CG (coarse_qn 0). */
+ * CG (coarse_qn 0), FGMRES outer solver. */
 void jfnk_default_options(jfnk_options *opt);
 
 /* Bytes of device workspace a context for (prob, opt) needs. */
@@ -315,7 +325,7 @@ typedef enum {
     JFNK_TIMER_CHEB_FINE = 0,   /* interior fused Chebyshev steps on the finest level */
     JFNK_TIMER_JV_OUTER = 1,    /* FP64 outer FD Jacobian action */
     JFNK_TIMER_RESID_FINE = 2,  /* FP64 finest-level residual */
-    JFNK_TIMER_ARNOLDI = 3,     /* Gram-Schmidt passes of FGMRES */
+    JFNK_TIMER_ARNOLDI = 3,     /* Gram-Schmidt passes of FGMRES; the vector steps of CG */
     JFNK_TIMER_COUNT = 4
 } jfnk_timer;
 /* enable != 0 starts recording (clearing earlier records); 0 stops. */

@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
                 ('ls_maxit', ctypes.c_int), ('armijo', ctypes.c_double), ('vcycle_prec', ctypes.c_int),
                 ('eps_mode', ctypes.c_int), ('fd_root', ctypes.c_double), ('forcing', ctypes.c_int),
                 ('merit', ctypes.c_int), ('seed', ctypes.c_ulonglong), ('kernel_path', ctypes.c_int),
-                ('fd_form', ctypes.c_int), ('coarse_qn', ctypes.c_int)]
+                ('fd_form', ctypes.c_int), ('coarse_qn', ctypes.c_int), ('outer_krylov', ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

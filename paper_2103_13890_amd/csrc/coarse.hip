@@ -34,8 +34,8 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
     constexpr int NV = Cell<DIM>::NV;
     const long long nn = g.nn, n = nn * NC;
     const long long ne = (long long)g.nx * g.ny * (DIM == 3 ? g.nz : 1);
-    // r, p, q, then the element contributions ew[(c * ne + e) * NV + a]
-    T *r = work, *p = work + n, *q = work + 2 * n, *ew = work + 3 * n;
+    // r, p, q, z, then the element contributions ew[(c * ne + e) * NV + a]
+    T *r = work, *p = work + n, *q = work + 2 * n, *z = work + 3 * n, *ew = work + 4 * n;
     CgSum cg_bsum;
     const double epsn = *num;
     const T h = (T)g.h;
@@ -114,6 +114,40 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
     long long fd = 0, iters = 0;
     bool s_nonzero = false;
 
+    // L-BFGS preconditioner (CG-QN), as in k_coarse_small below but with the
+    // vectors, recorded steps and pairs in global memory (entry k of a pair
+    // is touched by the thread that owns entry k of every vector)
+    T *rec_s = (T *)ca.qn_rec, *rec_y = rec_s ? rec_s + (size_t)ca.qn_cap * n : nullptr;
+    T *ps = (T *)ca.qn_pairs, *py = ps ? ps + (size_t)ca.qn_m * n : nullptr;
+    __shared__ double srho[QN_MAX], sa[QN_MAX];
+    const bool qn_on = ca.qn_m > 0;
+    bool recording = qn_on && ca.qn_state[0] == 0.0;
+    int np = (qn_on && !recording) ? (int)ca.qn_state[1] : 0;
+    double gam = np > 0 ? ca.qn_state[2] : 1.0;
+    if (threadIdx.x < np) srho[threadIdx.x] = ca.qn_state[3 + threadIdx.x];
+    __syncthreads();
+    int nrec = 0;
+    // z = H r by the two-loop recursion (np > 0)
+    auto prec = [&]() __attribute__((always_inline)) {
+        NODE_LOOP(i, n) z[i] = r[i];
+        for (int k = np - 1; k >= 0; --k) {
+            const T *sk = ps + (size_t)k * n, *yk = py + (size_t)k * n;
+            double d = 0.0;
+            NODE_LOOP(i, n) d += (double)sk[i] * (double)z[i];
+            const double ak = srho[k] * cg_bsum(d);
+            if (threadIdx.x == 0) sa[k] = ak;
+            NODE_LOOP(i, n) z[i] -= (T)ak * yk[i];
+        }
+        NODE_LOOP(i, n) z[i] = (T)gam * z[i];
+        for (int k = 0; k < np; ++k) {
+            const T *sk = ps + (size_t)k * n, *yk = py + (size_t)k * n;
+            double d = 0.0;
+            NODE_LOOP(i, n) d += (double)yk[i] * (double)z[i];
+            const double bk = srho[k] * cg_bsum(d);
+            NODE_LOOP(i, n) z[i] += (T)(sa[k] - bk) * sk[i];
+        }
+    };
+
     auto cg = [&](double shift) __attribute__((always_inline)) -> double {
         if (s_nonzero) {
             double ss = 0.0;
@@ -132,6 +166,18 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
         rr = cg_bsum(rr);
         if (sqrt(rr) <= tol) return 0.0;
         double pp = rr;             // ||p||^2, carried from the p update
+        double rz = rr;             // r.z (z = r without pairs)
+        if (np > 0) {
+            prec();
+            double d1 = 0.0, d2 = 0.0;
+            NODE_LOOP(i, n) {
+                p[i] = z[i];
+                d1 += (double)r[i] * (double)z[i];
+                d2 += (double)z[i] * (double)z[i];
+            }
+            rz = cg_bsum(d1);
+            pp = cg_bsum(d2);
+        }
         for (int it = 1; it <= ca.maxit; ++it) {
             apply(p, pp, shift);
             ++fd;
@@ -140,8 +186,16 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
             NODE_LOOP(i, n) pq += (double)p[i] * (double)q[i];
             pq = cg_bsum(pq);
             if (pq <= 0.0) return pq / pp;
-            const double alpha = rr / pq;
+            const double alpha = rz / pq;
             const T a = (T)alpha;
+            if (recording && nrec < ca.qn_cap) {
+                T *rs = rec_s + (size_t)nrec * n, *ry = rec_y + (size_t)nrec * n;
+                NODE_LOOP(i, n) {
+                    rs[i] = a * p[i];
+                    ry[i] = a * q[i];
+                }
+                ++nrec;
+            }
             double rn = 0.0;
             NODE_LOOP(i, n) {
                 s[i] += a * p[i];
@@ -152,21 +206,81 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
             s_nonzero = true;
             rn = cg_bsum(rn);
             if (sqrt(rn) <= tol) return 0.0;
-            const T beta = (T)(rn / rr);
             double pn = 0.0;
-            NODE_LOOP(i, n) {
-                const T pi = r[i] + beta * p[i];
-                p[i] = pi;
-                pn += (double)pi * (double)pi;
+            if (np > 0) {
+                prec();
+                double d = 0.0;
+                NODE_LOOP(i, n) d += (double)r[i] * (double)z[i];
+                const double rzn = cg_bsum(d);
+                const T beta = (T)(rzn / rz);
+                NODE_LOOP(i, n) {
+                    const T pi = z[i] + beta * p[i];
+                    p[i] = pi;
+                    pn += (double)pi * (double)pi;
+                }
+                rz = rzn;
+            } else {
+                const T beta = (T)(rn / rz);
+                NODE_LOOP(i, n) {
+                    const T pi = r[i] + beta * p[i];
+                    p[i] = pi;
+                    pn += (double)pi * (double)pi;
+                }
+                rz = rn;
             }
             pp = cg_bsum(pn);
-            rr = rn;
         }
         return 0.0;
     };
 
+    // after the recording CG: keep the uniform sample floor(k t / m) with
+    // positive curvature, oldest first; rho_k and gamma to the state
+    auto keep_pairs = [&]() __attribute__((always_inline)) {
+        const int t = nrec, m = ca.qn_m;
+        const int nsel = t <= m ? t : m;
+        int kept = 0;
+        double g_s = 0.0;
+        for (int k = 0; k < nsel; ++k) {
+            const int src = t <= m ? k : (int)(((long long)k * t) / m);
+            const T *rs = rec_s + (size_t)src * n, *ry = rec_y + (size_t)src * n;
+            double d = 0.0;
+            NODE_LOOP(i, n) d += (double)rs[i] * (double)ry[i];
+            const double sy = cg_bsum(d);
+            if (sy > 0.0) {
+                double d2 = 0.0;
+                T *qs = ps + (size_t)kept * n, *qy = py + (size_t)kept * n;
+                NODE_LOOP(i, n) {
+                    qs[i] = rs[i];
+                    qy[i] = ry[i];
+                    d2 += (double)ry[i] * (double)ry[i];
+                }
+                const double yy = cg_bsum(d2);
+                if (threadIdx.x == 0) {
+                    ca.qn_state[3 + kept] = 1.0 / sy;
+                    srho[kept] = 1.0 / sy;
+                }
+                g_s = sy / yy;
+                ++kept;
+            }
+        }
+        if (threadIdx.x == 0) {
+            ca.qn_state[0] = 1.0;
+            ca.qn_state[1] = (double)kept;
+            ca.qn_state[2] = kept > 0 ? g_s : 1.0;
+        }
+        __threadfence_block();
+        __syncthreads();
+        np = kept;
+        gam = kept > 0 ? g_s : 1.0;
+        recording = false;
+    };
+
     double shift = 0.0;
     double lam_c = cg(shift);
+    if (recording) {
+        __syncthreads();
+        keep_pairs();
+    }
     int rounds = 0;
     int negc = lam_c < 0.0 ? 1 : 0;
     while (lam_c < 0.0 && rounds < ca.shift_max) {
@@ -412,6 +526,12 @@ static size_t coarse_small_lds(const Grid &g, int kind, size_t eb) {
 }
 bool coarse_small(const Grid &g, int kind, size_t eb) {
     return kind != JFNK_NEOHOOKE && g.nn <= CBLOCK && coarse_small_lds(g, kind, eb) <= 64 * 1024;
+}
+// elements of the generic solver's work array: r, p, q, z and 2^d
+// contributions per element and component
+size_t coarse_work_elems(const Grid &g, int nc) {
+    const long long ne = (long long)g.nx * g.ny * (g.dim == 3 ? g.nz : 1);
+    return (size_t)(4 * g.nn * nc + (g.dim == 3 ? 8 : 4) * ne * nc);
 }
 
 template <int DIM, int KIND, typename T>

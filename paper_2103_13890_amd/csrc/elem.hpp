@@ -86,6 +86,10 @@ __device__ __forceinline__ T plap_pow(T base, double p, int which) {
         return which == 0 ? r : (which == 1 ? base * r : hw_div(T(1), r));
     }
     if (p == 2.0) return which == 0 ? T(1) : (which == 1 ? base : hw_div(T(1), base));
+    if (p == 1.0) {     // the minimal-surface energy: exponents -1/2, 1/2, -3/2
+        T r = hw_sqrt(base);
+        return which == 1 ? r : hw_div(T(1), which == 0 ? r : base * r);
+    }
     double e = which == 0 ? 0.5 * (p - 2.0) : (which == 1 ? 0.5 * p : 0.5 * (p - 4.0));
     return (T)pow(base, (T)e);
 }

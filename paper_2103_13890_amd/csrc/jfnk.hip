@@ -147,8 +147,6 @@ std::string validate(const jfnk_problem *p, const jfnk_options *o) {
         return "NEOHOOKE needs E > 0 and -1 < nu < 0.5";
     if (o->restart < 1 || o->restart > MAXR - 1) return "restart must be in [1, 31]";
     if (o->coarse_qn < 0 || o->coarse_qn > QN_MAX) return "coarse_qn must be in [0, 32]";
-    if (o->coarse_qn > 0 && !coarse_small(level_grid(*p, 0), p->kind, esize(o->vcycle_prec)))
-        return "coarse_qn needs a scalar kind with at most 1024 coarse nodes";
     if (o->nu_pre < 0 || o->nu_post < 0) return "smoothing degrees must be >= 0";
     if (o->vcycle_prec != JFNK_F32 && o->vcycle_prec != JFNK_F64) return "vcycle_prec must be F32 or F64";
     if (o->eps_mode != JFNK_EPS_NORM && o->eps_mode != JFNK_EPS_PAPER) return "unknown eps_mode";
@@ -156,6 +154,8 @@ std::string validate(const jfnk_problem *p, const jfnk_options *o) {
     if (o->power_maxit < 1) return "power_maxit must be >= 1";
     if (o->fd_form < 0 || o->fd_form > 2) return "fd_form must be 0, 1 or 2";
     if (o->kernel_path < 0 || o->kernel_path > 2) return "kernel_path must be 0, 1 or 2";
+    if (o->outer_krylov != JFNK_OUTER_FGMRES && o->outer_krylov != JFNK_OUTER_CG)
+        return "outer_krylov must be FGMRES or CG";
     if (o->newton_maxit < 0 || o->max_cycles < 1 || o->ls_maxit < 1) return "iteration caps must be positive";
     Grid g0 = level_grid(*p, 0);
     if (g0.nn > coarse_max_nodes()) return "coarsest grid too large for the coarse solver: add levels";
@@ -195,8 +195,8 @@ void plan(jfnk_ctx *c, Carve &cv) {
         L.t = cv.take(vb);
         L.eig = cv.take(vb);
         L.q = cv.take(vb);
-        // coarse solver: r, p, q and the per-element contributions (8 per element)
-        L.cw = l == 0 ? cv.take(11 * vb) : nullptr;
+        // coarse solver: r, p, q, z and the per-element contributions
+        L.cw = l == 0 ? cv.take(coarse_work_elems(L.g, nc) * es) : nullptr;
     }
     if (c->opt.coarse_qn > 0) {
         const Grid &g0 = c->lev[0].g;
@@ -732,6 +732,69 @@ jfnk_status run_fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, d
 }
 
 // ---------------------------------------------------------------------------
+// preconditioned CG, the paper's CG-MG (Sec. 3, setup): z = M r by one
+// V-cycle, at most restart * max_cycles steps; a direction with p.Ap <= 0
+// ends the solve unconverged with x as it stands.  Vectors: r and p in the
+// first two basis columns, q = A p in w, z in the first preconditioned
+// column.  One host read per step (p.Ap and ||r||^2 after the update).
+// ---------------------------------------------------------------------------
+template <typename T>
+jfnk_status pcg(jfnk_ctx *c, OpKind op, const double *rhs, double sign, double rhs_norm, double tol, double *x,
+                int *iters, double *est_out) {
+    const Grid &g = c->lev[c->L].g;
+    const long long n = c->n;
+    double *r = c->V, *p = c->V + n;
+    T *z = (T *)c->Z;
+    // slots: p.Ap, ||r||^2 (read together), r.z of this and the previous step, ||p||^2
+    double *s_pq = slot(c, S_COEF), *s_rn2 = slot(c, S_COEF + 1), *s_rz[2] = {slot(c, S_COEF + 2),
+                                                                               slot(c, S_COEF + 3)};
+    double *s_pn2 = slot(c, S_COEF + 4);
+    vec_fill<double>(c->ex, x, n, 0.0);
+    *iters = 0;
+    *est_out = rhs_norm;
+    if (rhs_norm <= tol) return JFNK_OK;
+    vec_scale<double>(c->ex, g, c->nc, rhs, r, sign, nullptr, nullptr);
+    const int maxit = c->opt.restart * c->opt.max_cycles;
+    int cur = 0;
+    for (int it = 1; it <= maxit; ++it) {
+        precondition<T>(c, r, nullptr, z);
+        {
+            TimeScope ts(c, JFNK_TIMER_ARNOLDI, false);
+            vec_dot<double, T>(c->ex, n, r, z, s_rz[cur]);
+            vec_cg_dir<T>(c->ex, n, z, p, s_rz[cur], it == 1 ? nullptr : s_rz[cur ^ 1], s_pn2);
+        }
+        CHK(apply_op<double>(c, op, p, s_pn2, c->w));
+        {
+            TimeScope ts(c, JFNK_TIMER_ARNOLDI, false);
+            vec_dot<double, double>(c->ex, n, p, c->w, s_pq);
+            vec_cg_update(c->ex, n, p, c->w, x, r, s_rz[cur], s_pq, s_rn2);
+        }
+        CHK(check_launch(c));
+        double h[2];
+        CHK(read_slots(c, S_COEF, 2, h));
+        *iters = it;
+        if (!std::isfinite(h[0])) return fail(c, JFNK_E_NONFINITE, "CG: non-finite curvature");
+        if (!(h[0] > 0.0)) return JFNK_E_NOCONV;           // x and r unchanged by this step
+        const double rn = std::sqrt(h[1]);
+        if (!std::isfinite(rn)) return fail(c, JFNK_E_NONFINITE, "CG: non-finite residual");
+        *est_out = rn;
+        if (rn <= tol) return JFNK_OK;
+        cur ^= 1;
+    }
+    return JFNK_E_NOCONV;
+}
+
+// the Newton step's outer solve with the configured Krylov method
+jfnk_status run_outer(jfnk_ctx *c, const double *rhs, double sign, double rhs_norm, double tol, double *x,
+                      int *iters, double *est) {
+    if (c->opt.outer_krylov == JFNK_OUTER_CG) {
+        if (c->vprec == JFNK_F32) return pcg<float>(c, OP_FD, rhs, sign, rhs_norm, tol, x, iters, est);
+        return pcg<double>(c, OP_FD, rhs, sign, rhs_norm, tol, x, iters, est);
+    }
+    return run_fgmres(c, OP_FD, rhs, sign, rhs_norm, tol, x, iters, est);
+}
+
+// ---------------------------------------------------------------------------
 // inexact Newton with cubic backtracking (Sec. 3, setup)
 // ---------------------------------------------------------------------------
 bool variational(int kind) { return kind != JFNK_INVCOEF; }
@@ -833,7 +896,7 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
                             slot(c, S_NUM64));
         int its = 0;
         double est = 0.0;
-        jfnk_status ks = run_fgmres(c, OP_FD, c->F, -1.0, fn, eta * fn, c->dx, &its, &est);
+        jfnk_status ks = run_outer(c, c->F, -1.0, fn, eta * fn, c->dx, &its, &est);
         if (ks == JFNK_E_NONFINITE || ks == JFNK_E_DEVICE) return ks;
         rep->linear_iters += its;
         // line search
@@ -952,6 +1015,8 @@ void jfnk_default_options(jfnk_options *o) {
     o->seed = 0;
     o->kernel_path = 0;
     o->fd_form = 0;
+    o->coarse_qn = 0;
+    o->outer_krylov = JFNK_OUTER_FGMRES;
 }
 
 jfnk_status jfnk_workspace_bytes(const jfnk_problem *p, const jfnk_options *o, size_t *bytes) {

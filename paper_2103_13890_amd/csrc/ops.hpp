@@ -159,6 +159,14 @@ void dcgs_update(const Exec &, long long n, double *V, long long ld, int J, cons
 template <typename TZ>
 void arn_combine(const Exec &, long long n, const TZ *Z, long long ld, int k, const double *y, double *x);
 // y = x + a d (FP64)
+// preconditioned CG: x += a p, r -= a q with a = *rz / *pq when *pq > 0
+// (else nothing), ||r||^2 -> rn2; and p = z + (*rz / *rz_prev) p (rz_prev
+// null: p = z), ||p||^2 -> pn2
+void vec_cg_update(const Exec &, long long n, const double *p, const double *q, double *x, double *r,
+                   const double *rz, const double *pq, double *rn2);
+template <typename TZ>
+void vec_cg_dir(const Exec &, long long n, const TZ *z, double *p, const double *rz, const double *rz_prev,
+                double *pn2);
 void vec_axpy(const Exec &, long long n, const double *x, double a, const double *d, double *y);
 
 // ---- transfers (level l fine, l-1 coarse) -----------------------------------------
@@ -188,6 +196,8 @@ struct CoarseArgs {
 // whether the coarse solve of this level runs in the one-workgroup kernel
 // that keeps the level in LDS (the one that supports the L-BFGS preconditioner)
 bool coarse_small(const Grid &, int kind, size_t elem_bytes);
+// elements of the work array the generic coarse solver needs
+size_t coarse_work_elems(const Grid &, int nc);
 template <typename T>
 void coarse_solve(const Exec &, int mode, const Grid &, const Phys &, const T *kap, const T *x, const T *Ax,
                   const double *num, const T *b, T *s, T *work, const CoarseArgs &);

@@ -249,6 +249,64 @@ void vec_dot(const Exec &ex, long long n, const TA *x, const TB *y, double *out)
 template void vec_dot<double, double>(const Exec &, long long, const double *, const double *, double *);
 template void vec_dot<float, float>(const Exec &, long long, const float *, const float *, double *);
 
+template void vec_dot<double, float>(const Exec &, long long, const double *, const float *, double *);
+
+// ---- preconditioned CG steps --------------------------------------------------------
+// x += a p, r -= a q with a = rz / pq, ||r||^2 -> rn2; nothing is updated
+// unless pq > 0 (the negative-curvature exit keeps x and r)
+__global__ void k_cg_update(long long n, const double *p, const double *q, double *x, double *r, const double *rz,
+                            const double *pq, Red red) {
+    const double c = *pq;
+    const bool go = c > 0.0;
+    const double a = go ? *rz / c : 0.0;
+    double sm[1] = {0.0};
+    if (go) {
+        GRID_STRIDE(i, n) {
+            x[i] += a * p[i];
+            const double ri = r[i] - a * q[i];
+            r[i] = ri;
+            sm[0] += ri * ri;
+        }
+    }
+    block_partials<1>(sm, red);
+}
+void vec_cg_update(const Exec &ex, long long n, const double *p, const double *q, double *x, double *r,
+                   const double *rz, const double *pq, double *rn2) {
+    materialize(ex, const_cast<double *>(rz));
+    materialize(ex, const_cast<double *>(pq));
+    const int nb = vblocks(n);
+    const Red rd = red_for(ex, rn2, nb);
+    k_cg_update<<<nb, BLOCK, 0, ex.st>>>(n, p, q, x, r, rz, pq, rd);
+    finish_to<1>(ex, rn2, rd, nb, FinStore<1>{rn2});
+}
+
+// p = z + b p with b = rz / rz_prev (rz_prev null: p = z), ||p||^2 -> pn2
+template <typename TZ>
+__global__ void k_cg_dir(long long n, const TZ *z, double *p, const double *rz, const double *rz_prev, Red red) {
+    const double b = rz_prev ? *rz / *rz_prev : 0.0;
+    double sm[1] = {0.0};
+    GRID_STRIDE(i, n) {
+        const double v = rz_prev ? (double)z[i] + b * p[i] : (double)z[i];
+        p[i] = v;
+        sm[0] += v * v;
+    }
+    block_partials<1>(sm, red);
+}
+template <typename TZ>
+void vec_cg_dir(const Exec &ex, long long n, const TZ *z, double *p, const double *rz, const double *rz_prev,
+                double *pn2) {
+    materialize(ex, const_cast<double *>(rz));
+    if (rz_prev) materialize(ex, const_cast<double *>(rz_prev));
+    const int nb = vblocks(n);
+    const Red rd = red_for(ex, pn2, nb);
+    k_cg_dir<TZ><<<nb, BLOCK, 0, ex.st>>>(n, z, p, rz, rz_prev, rd);
+    finish_to<1>(ex, pn2, rd, nb, FinStore<1>{pn2});
+}
+template void vec_cg_dir<float>(const Exec &, long long, const float *, double *, const double *, const double *,
+                                double *);
+template void vec_cg_dir<double>(const Exec &, long long, const double *, double *, const double *, const double *,
+                                 double *);
+
 __global__ void k_axpy(long long n, const double *x, double a, const double *d, double *y) {
     GRID_STRIDE(i, n) y[i] = x[i] + a * d[i];
 }

@@ -22,6 +22,10 @@ Workloads (all synthetic; the paper uses analytic PDEs, no datasets):
 * bratu2d-800     the paper's Bratu experiment on Q1 elements: lam = 5, a
                   25 x 25 coarse mesh refined five times (800 x 800, 6
                   levels), solved with the paper's settings (PAPER_OPTIONS)
+* beam3d-160x16x16 the paper's hyperelastic beam (0, 10) x (0, 1)^2: Neo-Hookean,
+                  E = 10, nu = 0.3, clamped at x = 0, the rotational data
+                  u_2 at x = 10, no load; the 10 x 1 x 1 coarse mesh refined
+                  four times (5 levels); paper settings
 * minsurf2d-800   the paper's minimal-surface experiment on the same
                   hierarchy: the p-Laplacian energy with p = 1, delta = 1 is
                   int sqrt(1 + |grad u|^2); u = 0 on x = 0, 1 and u = x(1 - x)
@@ -131,6 +135,14 @@ def dirichlet_state(w):
         x = np.arange(n[0] + 1) * h
         u[0, :] = x * (1.0 - x)
         u[-1, :] = x * (1.0 - x)
+    if w.get('dirichlet_data') == 'rotation':
+        # the end face x = n_x h of the beam (Sec. 3, hyperelasticity): half the
+        # displacement of a pi/6 rotation of (y, z) about (1/2, 1/2)
+        c, s = np.cos(np.pi / 6), np.sin(np.pi / 6)
+        y = (np.arange(n[1] + 1) * h)[None, :]
+        z = (np.arange(n[2] + 1) * h)[:, None]
+        u[1, :, :, -1] = 0.5 * (0.5 + (y - 0.5) * c - (z - 0.5) * s - y)
+        u[2, :, :, -1] = 0.5 * (0.5 + (y - 0.5) * s + (z - 0.5) * c - z)
     return u
 
 
@@ -161,6 +173,9 @@ WORKLOADS = {
                         options=dict(PAPER_OPTIONS)),
     'minsurf2d-800': dict(kind='plap', n=(800, 800), h=1 / 800, faces=ALL2, params=(1.0, 1.0), nlevels=6,
                           dirichlet_data='minsurf', options=dict(PAPER_OPTIONS)),
+    'beam3d-160x16x16': dict(kind='neohooke', n=(160, 16, 16), h=1 / 16, faces=[(0, 0), (0, 1)],
+                             params=(10.0, 0.3), nlevels=5, dirichlet_data='rotation',
+                             options=dict(PAPER_OPTIONS)),
 }
 
 

@@ -68,6 +68,12 @@ def small(kind):
         return w
     if kind == 'plap':
         return W.scaled('plap3d-128', (36, 20, 12), nlevels=3, vcycle_prec=0, coarse_rtol=1e-6)
+    if kind == 'minsurf':
+        # the minimal-surface energy (p-Laplacian, p = 1, delta = 1) in 2D,
+        # with the generic solver options of the small Bratu case
+        w = W.scaled('bratu2d-32', (36, 20), nlevels=3)
+        w.update(kind='plap', params=(1.0, 1.0))
+        return w
     if kind == 'invcoef':
         return W.scaled('invcoef3d-128', (36, 20, 12), nlevels=3)
     if kind == 'neohooke':

@@ -27,7 +27,7 @@ from oracle import transfer as OT
 from paper_2103_13890_amd import api
 from paper_2103_13890_amd import workloads as W
 
-KINDS = ['bratu2d', 'bratu3d', 'plap', 'invcoef', 'neohooke']
+KINDS = ['bratu2d', 'bratu3d', 'plap', 'minsurf', 'invcoef', 'neohooke']
 
 
 def _inputs(w, seed, smooth=False):
@@ -222,7 +222,7 @@ def _setup_both(w, u, m, **mg_over):
     return ctx, levels, opts
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'invcoef', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'invcoef', 'neohooke'])
 @pytest.mark.parametrize('form', [1, 2])
 def test_mg_setup(kind, form):
     w = small(kind)
@@ -237,7 +237,7 @@ def test_mg_setup(kind, form):
             assert rel(to_np(api.mg_get_level(ctx, l, 'eig')), lev.eig) < 1e-9
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'neohooke'])
 @pytest.mark.parametrize('form', [1, 2])
 def test_smoother(kind, form):
     w = small(kind)
@@ -285,7 +285,7 @@ def test_coarse_solve_spd_and_shift():
         assert rel(to_np(s), ref) < 1e-9
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'invcoef', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'invcoef', 'neohooke'])
 @pytest.mark.parametrize('form', [1, 2])
 def test_vcycle(kind, form):
     w = small(kind)
@@ -312,7 +312,7 @@ def test_vjp(kind):
         assert rel(to_np(gm), OD.vjp_coef(pb, g, u, v, m)) < 1e-12
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'neohooke'])
 def test_energy(kind):
     w = small(kind)
     ctx = make_ctx(w)
