@@ -11,7 +11,9 @@ The same solve with FP64 levels is timed for comparison.
 Printed JSON line: value = DoF / (seconds per solve) of the FP32-multigrid
 solve; roofline = the fine-level kernel class with the largest share of the
 timed region, measured with HIP events around each of its launches;
-fine_residual = FP64 F(u) GB/s over rotating buffers; cpu_baseline = the
+fine_residual = FP64 F(u) GB/s over rotating buffers (and the same with the
+p-Laplacian coefficient at each Gauss point, against the FP64 VALU peak);
+cpu_baseline = the
 NumPy oracle on the host (see --help).  The paper's own experiments (Bratu
 and minimal surface on 800 x 800 elements, the Neo-Hookean beam on
 160 x 16 x 16, with its solver settings: CG-MG, V(5, 5), shifted coarse
@@ -155,6 +157,32 @@ def residual_gbps(ctx, w, nsets=4, launches=100):
             'bytes_per_launch': 24 * nn, 'buffers': f'{nsets} rotating sets of u, b, F (FP64)'}
 
 
+# FP64 operations per element of the Gauss-point p-Laplacian residual as the
+# element routine is written (an FMA counts 2, a square root 1): gradients at
+# the Gauss points 84, |g_q|^2 and the coefficient 8 x 8, fluxes 24, the
+# scatter back to the corners 104
+GAUSS_FLOPS_PER_ELEM = 84 + 64 + 24 + 104
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def gauss_residual(w):
+    """FP64 F(u) of the p-Laplacian with its coefficient at each of the 8
+    Gauss points (instead of the element mean) on the same grid: HBM rate
+    and FP64 VALU rate."""
+    from paper_2103_13890_amd import api
+    prob = api.make_problem('plap_gauss', w['n'], w['h'], w['faces'], w['params'], w['nlevels'])
+    ctx = api.Context(prob, api.default_options(vcycle_prec=0))
+    r = residual_gbps(ctx, w)
+    ne = 1
+    for k in w['n']:
+        ne *= k
+    tf = GAUSS_FLOPS_PER_ELEM * ne / (r['avg_us'] * 1e-6) / 1e12
+    r.update({'flops_per_element': GAUSS_FLOPS_PER_ELEM, 'tflops_fp64': tf,
+              'frac_fp64_valu': tf / FP64_VALU_PEAK_TFLOPS, 'valu_peak_tflops': FP64_VALU_PEAK_TFLOPS})
+    del ctx
+    return r
+
+
 def cpu_baseline(w, ge_effective, ndof):
     """Oracle sample: fine-level F(u) evaluations at full size on the host."""
     from oracle.fe import Grid
@@ -263,6 +291,8 @@ def main():
                     help='skip the FP32-MG solve with the L-BFGS coarse preconditioner (CG-QN)')
     ap.add_argument('--no-paper', action='store_true',
                     help="skip the paper's three experiments solved with its solver settings")
+    ap.add_argument('--no-gauss', action='store_true',
+                    help='skip the FP64 residual with the coefficient at each Gauss point')
     ap.add_argument('--kernel-path', type=int, default=0)
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a 1 GiB device copy (to scale HBM counters) and exit')
@@ -374,6 +404,12 @@ def main():
         except Exception as e:      # the check is informative only
             extra['oracle_sampled_residual'] = f'skipped: {e}'
         del ctxt
+    if w['kind'] == 'plap' and not args.no_gauss:
+        torch.cuda.empty_cache()
+        fg = gauss_residual(w)
+        extra['fine_residual_f64_gauss'] = fg
+        log(f'fine F(u) FP64, coefficient at the Gauss points: {fg["avg_us"]:.1f} us, {fg["gbps"]:.0f} GB/s, '
+            f'{fg["tflops_fp64"]:.1f} TFLOP/s FP64')
     if not args.no_paper:
         extra['paper_settings'] = paper_mode_solves(max(1, min(args.steps, 3)))
     cpu = None

@@ -60,7 +60,9 @@ typedef enum {
     JFNK_BRATU = 0,     /* Psi = int 1/2|grad u|^2 - lam e^u; Gauss 2^d points    */
     JFNK_PLAP = 1,      /* regularised p-Laplacian, element-mean coefficient      */
     JFNK_INVCOEF = 2,   /* -div(e^m (1+u^2) grad u) = f, element-mean coefficient  */
-    JFNK_NEOHOOKE = 3   /* compressible Neo-Hookean solid, Gauss 2x2x2, 3 comps   */
+    JFNK_NEOHOOKE = 3,  /* compressible Neo-Hookean solid, Gauss 2x2x2, 3 comps   */
+    JFNK_PLAP_GAUSS = 4 /* regularised p-Laplacian, coefficient at each of the 2^d
+                           Gauss points; param p, delta as for PLAP             */
 } jfnk_kind;
 
 typedef enum { JFNK_F64 = 0, JFNK_F32 = 1 } jfnk_prec;

@@ -10,13 +10,14 @@ MAX_HIST = 128
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOCONV, E_BREAKDOWN, E_NONFINITE = range(7)
 STATUS = {0: 'ok', 1: 'inval', 2: 'nomem', 3: 'device', 4: 'noconv', 5: 'breakdown', 6: 'nonfinite'}
-BRATU, PLAP, INVCOEF, NEOHOOKE = range(4)
+BRATU, PLAP, INVCOEF, NEOHOOKE, PLAP_GAUSS = range(5)
+OUTER_FGMRES, OUTER_CG = 0, 1
 F64, F32 = 0, 1
 EPS_NORM, EPS_PAPER = 0, 1
 FORCING_RELATIVE, FORCING_PAPER = 0, 1
 MERIT_AUTO, MERIT_RESIDUAL = 0, 1
 TIMER_CHEB_FINE, TIMER_JV_OUTER, TIMER_RESID_FINE, TIMER_ARNOLDI = range(4)
-KINDS = {'bratu': BRATU, 'plap': PLAP, 'invcoef': INVCOEF, 'neohooke': NEOHOOKE}
+KINDS = {'bratu': BRATU, 'plap': PLAP, 'invcoef': INVCOEF, 'neohooke': NEOHOOKE, 'plap_gauss': PLAP_GAUSS}
 
 
 class Problem(ctypes.Structure):

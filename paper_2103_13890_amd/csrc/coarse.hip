@@ -572,6 +572,10 @@ void coarse_solve(const Exec &ex, int mode, const Grid &g, const Phys &ph, const
     case JFNK_NEOHOOKE:
         launch_coarse<3, JFNK_NEOHOOKE, T>(ex, mode, g, ph, kap, x, Ax, num, b, s, work, ca);
         break;
+    case JFNK_PLAP_GAUSS:
+        if (g.dim == 2) launch_coarse<2, JFNK_PLAP_GAUSS, T>(ex, mode, g, ph, kap, x, Ax, num, b, s, work, ca);
+        else launch_coarse<3, JFNK_PLAP_GAUSS, T>(ex, mode, g, ph, kap, x, Ax, num, b, s, work, ca);
+        break;
     }
 }
 template void coarse_solve<float>(const Exec &, int, const Grid &, const Phys &, const float *, const float *,

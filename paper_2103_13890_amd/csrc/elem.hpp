@@ -6,6 +6,8 @@
 //
 //   BRATU    r_a = (K u)_a - lam sum_q w_q exp(u_h(x_q)) phi_a(x_q)
 //   PLAP     r_a = (delta^2 + s)^((p-2)/2) (K u)_a,   s = u^T K u / |e|
+//   PLAP_GAUSS  r_a = sum_q w_q k_q grad phi_a(x_q) . g_q,  g_q = grad u_h(x_q),
+//               k_q = (delta^2 + |g_q|^2)^((p-2)/2)
 //   INVCOEF  r_a = kbar (1 + ubar^2) (K u)_a,          kbar = mean e^{m}, ubar = mean u
 //   NEOHOOKE r_{i,a} = sum_q w_q P_ij(F_q) d_j phi_a(x_q),
 //            P = mu (F - F^-T) + lam ln J F^-T,  F = I + grad u
@@ -95,6 +97,166 @@ __device__ __forceinline__ T plap_pow(T base, double p, int which) {
 }
 
 // ---------------------------------------------------------------------------
+// Gradients at the Gauss points (PLAP_GAUSS).  In reference units G = h g.
+// Inside a Q1 cell the derivative along axis i does not vary along i, so G_i
+// takes 2^(d-1) values: the tensor interpolation of the 2^(d-1) edge
+// differences along i, with weights W(b, q) = GL1 if b == q else GL0 on each
+// other axis.  W is symmetric, so the same interpolation maps per-point
+// fluxes back to the corners.  Index j of the other axes: lower axis first.
+// ---------------------------------------------------------------------------
+template <int DIM> __device__ __forceinline__ constexpr int gq_corner(int i, int b, int j) {
+    if (DIM == 2) return (b << i) | (j << (1 - i));
+    return (b << i) | ((j & 1) << (i == 0 ? 1 : 0)) | (((j >> 1) & 1) << (i == 2 ? 1 : 2));
+}
+template <int DIM> __device__ __forceinline__ constexpr int gq_other(int i, int q) {
+    if (DIM == 2) return (q >> (1 - i)) & 1;
+    return ((q >> (i == 0 ? 1 : 0)) & 1) | (((q >> (i == 2 ? 1 : 2)) & 1) << 1);
+}
+template <int DIM, typename T> __device__ __forceinline__ void gq_interp(const T *in, T *out) {
+    const T A = T(GL1), B = T(GL0);
+    if (DIM == 2) {
+        out[0] = A * in[0] + B * in[1];
+        out[1] = B * in[0] + A * in[1];
+    } else {
+        const T t0 = A * in[0] + B * in[1], t1 = B * in[0] + A * in[1];
+        const T t2 = A * in[2] + B * in[3], t3 = B * in[2] + A * in[3];
+        out[0] = A * t0 + B * t2;
+        out[1] = A * t1 + B * t3;
+        out[2] = B * t0 + A * t2;
+        out[3] = B * t1 + A * t3;
+    }
+}
+template <int DIM, typename T> __device__ __forceinline__ void gq_grad(const T *u, T (*G)[1 << (DIM - 1)]) {
+    constexpr int NH = 1 << (DIM - 1);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        T e[NH];
+#pragma unroll
+        for (int j = 0; j < NH; ++j) e[j] = u[gq_corner<DIM>(i, 1, j)] - u[gq_corner<DIM>(i, 0, j)];
+        gq_interp<DIM, T>(e, G[i]);
+    }
+}
+// |G_q|^2 and G_q . H_q at Gauss point q
+template <int DIM, typename T>
+__device__ __forceinline__ T gq_dot(const T (*G)[1 << (DIM - 1)], const T (*H)[1 << (DIM - 1)], int q) {
+    T d = T(0);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) d += G[i][gq_other<DIM>(i, q)] * H[i][gq_other<DIM>(i, q)];
+    return d;
+}
+// r_a = c sum_i s_i(a) (interp F_i)[j(a)], s_i(a) = +1 if corner a has bit i, else -1;
+// F_i[j] is the flux along i summed over the two Gauss points that share j
+template <int DIM, typename T>
+__device__ __forceinline__ void gq_scatter(T (*F)[1 << (DIM - 1)], T c, T *r) {
+    constexpr int NH = 1 << (DIM - 1);
+    T E[DIM][NH];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) gq_interp<DIM, T>(F[i], E[i]);
+#pragma unroll
+    for (int a = 0; a < (1 << DIM); ++a) {
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            const T e = E[i][gq_other<DIM>(i, a)];
+            acc += ((a >> i) & 1) ? e : -e;
+        }
+        r[a] = c * acc;
+    }
+}
+// Sum over the pair of Gauss points that differ only along axis i.
+template <int DIM, typename T> __device__ __forceinline__ T gq_pair(const T *k, int i, int j) {
+    return k[gq_corner<DIM>(i, 0, j)] + k[gq_corner<DIM>(i, 1, j)];
+}
+
+// PLAP_GAUSS element vector; c = m |e| / (2^d h^2) (= m h^(d-2) / 2^d)
+template <int DIM, typename T>
+__device__ __forceinline__ void elem_plap_gauss(const T *w, const Phys &ph, T h, T *r, T m) {
+    constexpr int NV = Cell<DIM>::NV, NH = NV / 2;
+    T G[DIM][NH];
+    gq_grad<DIM, T>(w, G);
+    const T ih2 = T(1) / (h * h), d2 = T(ph.a1) * T(ph.a1);
+    T k[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) k[q] = plap_pow<T>(d2 + gq_dot<DIM, T>(G, G, q) * ih2, ph.a0, 0);
+    T F[DIM][NH];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < NH; ++j) F[i][j] = G[i][j] * gq_pair<DIM, T>(k, i, j);
+    const T hs = (DIM == 3) ? h : T(1);
+    const bool on = m != T(0);
+    gq_scatter<DIM, T>(F, on ? m * hs * T(1.0 / NV) : T(0), r);
+}
+
+// PLAP_GAUSS FD quotient in difference form: per Gauss point
+// k_w - k_x from s_w - s_x = eps (2 g_x . g_v + eps |g_v|^2), as for PLAP
+template <int DIM, typename T, int PF>
+__device__ __forceinline__ void elem_plap_gauss_fd(const T *x, const T *v, T eps, const Phys &ph, T h, T *q_out,
+                                                   T m) {
+    constexpr int NV = Cell<DIM>::NV, NH = NV / 2;
+    T Gx[DIM][NH], Gv[DIM][NH];
+    gq_grad<DIM, T>(x, Gx);
+    gq_grad<DIM, T>(v, Gv);
+    const T ih2 = T(1) / (h * h), d2 = T(ph.a1) * T(ph.a1);
+    T kw[NV], dk[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const T bx = d2 + gq_dot<DIM, T>(Gx, Gx, q) * ih2;
+        const T dsq = (T(2) * gq_dot<DIM, T>(Gx, Gv, q) + eps * gq_dot<DIM, T>(Gv, Gv, q)) * ih2;
+        const T bw = bx + eps * dsq;
+        if (PF == 3 || ph.a0 == 3.0) {
+            const T kx = hw_sqrt(bx);
+            kw[q] = hw_sqrt(bw);
+            dk[q] = hw_div(dsq, kw[q] + kx);
+        } else if (ph.a0 == 2.0) {
+            kw[q] = T(1);
+            dk[q] = T(0);
+        } else {
+            const T al = T(0.5 * (ph.a0 - 2.0));
+            const T kx = (T)pow(bx, al);
+            const T em = expm1(al * log1p(eps * dsq / bx));
+            kw[q] = kx * (T(1) + em);
+            dk[q] = kx * em / eps;
+        }
+    }
+    T F[DIM][NH];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < NH; ++j)
+            F[i][j] = Gv[i][j] * gq_pair<DIM, T>(kw, i, j) + Gx[i][j] * gq_pair<DIM, T>(dk, i, j);
+    const T hs = (DIM == 3) ? h : T(1);
+    const bool on = m != T(0);
+    gq_scatter<DIM, T>(F, on ? m * hs * T(1.0 / NV) : T(0), q_out);
+}
+
+// PLAP_GAUSS exact J_e lam (symmetric): per Gauss point
+// k_q g_lam + (p - 2) (delta^2 + |g|^2)^((p-4)/2) (g . g_lam) g
+template <int DIM, typename T>
+__device__ __forceinline__ void elem_plap_gauss_vjp(const T *w, const T *lam, const Phys &ph, T h, T *r) {
+    constexpr int NV = Cell<DIM>::NV, NH = NV / 2;
+    T G[DIM][NH], L[DIM][NH];
+    gq_grad<DIM, T>(w, G);
+    gq_grad<DIM, T>(lam, L);
+    const T ih2 = T(1) / (h * h), d2 = T(ph.a1) * T(ph.a1);
+    T k[NV], cm[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const T b = d2 + gq_dot<DIM, T>(G, G, q) * ih2;
+        k[q] = plap_pow<T>(b, ph.a0, 0);
+        cm[q] = T(ph.a0 - 2.0) * plap_pow<T>(b, ph.a0, 2) * gq_dot<DIM, T>(G, L, q) * ih2;
+    }
+    T F[DIM][NH];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < NH; ++j)
+            F[i][j] = L[i][j] * gq_pair<DIM, T>(k, i, j) + G[i][j] * gq_pair<DIM, T>(cm, i, j);
+    const T hs = (DIM == 3) ? h : T(1);
+    gq_scatter<DIM, T>(F, hs * T(1.0 / NV), r);
+}
+
+// ---------------------------------------------------------------------------
 // scalar kinds: r[a] for one element.  w: state corners, kap: e^{m} corners
 // ---------------------------------------------------------------------------
 // m multiplies the whole element vector (0 switches an element off without
@@ -103,6 +265,10 @@ __device__ __forceinline__ T plap_pow(T base, double p, int which) {
 // rather than multiplied by 0.
 template <int DIM, int KIND, typename T, int PF = 0>
 __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys &ph, T h, T *r, T m = T(1)) {
+    if constexpr (KIND == JFNK_PLAP_GAUSS) {
+        elem_plap_gauss<DIM, T>(w, ph, h, r, m);
+        return;
+    }
     constexpr int NV = Cell<DIM>::NV;
     constexpr double KS = KScale<DIM>::value;
     T Ku[NV];
@@ -154,6 +320,16 @@ __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys
 template <int DIM, int KIND, typename T>
 __device__ __forceinline__ T elem_scalar_energy(const T *w, const Phys &ph, T h) {
     constexpr int NV = Cell<DIM>::NV;
+    if constexpr (KIND == JFNK_PLAP_GAUSS) {   // sum_q |e|/2^d (delta^2 + |g_q|^2)^(p/2) / p
+        T G[DIM][NV / 2];
+        gq_grad<DIM, T>(w, G);
+        const T ih2 = T(1) / (h * h), d2 = T(ph.a1) * T(ph.a1);
+        T acc = T(0);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc += plap_pow<T>(d2 + gq_dot<DIM, T>(G, G, q) * ih2, ph.a0, 1);
+        const T vol = (DIM == 3) ? h * h * h : h * h;
+        return vol / (T(NV) * T(ph.a0)) * acc;
+    }
     T Ku[NV];
     stiff_apply<DIM, T>(w, Ku);
     const T hs = (DIM == 3) ? h : T(1);
@@ -190,6 +366,10 @@ __device__ __forceinline__ T elem_scalar_energy(const T *w, const Phys &ph, T h)
 template <int DIM, int KIND, typename T, int PF = 0>
 __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *kap, T eps, const Phys &ph,
                                                T h, T *q, T m = T(1)) {
+    if constexpr (KIND == JFNK_PLAP_GAUSS) {
+        elem_plap_gauss_fd<DIM, T, PF>(x, v, eps, ph, h, q, m);
+        return;
+    }
     constexpr int NV = Cell<DIM>::NV;
     constexpr double KS = KScale<DIM>::value;
     const T hs = (DIM == 3) ? h : T(1);
@@ -271,6 +451,10 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
 template <int DIM, int KIND, typename T>
 __device__ __forceinline__ void elem_scalar_vjp(const T *w, const T *kap, const T *lam, const Phys &ph,
                                                 T h, T *r) {
+    if constexpr (KIND == JFNK_PLAP_GAUSS) {
+        elem_plap_gauss_vjp<DIM, T>(w, lam, ph, h, r);
+        return;
+    }
     constexpr int NV = Cell<DIM>::NV;
     const T hs = (DIM == 3) ? h : T(1);
     T Kl[NV];

@@ -130,7 +130,7 @@ long long level_dofs(const Grid &g, int nc) {
 
 std::string validate(const jfnk_problem *p, const jfnk_options *o) {
     if (!p || !o) return "null problem or options";
-    if (p->kind < JFNK_BRATU || p->kind > JFNK_NEOHOOKE) return "unknown problem kind";
+    if (p->kind < JFNK_BRATU || p->kind > JFNK_PLAP_GAUSS) return "unknown problem kind";
     if (p->dim != 2 && p->dim != 3) return "dim must be 2 or 3";
     if (p->kind == JFNK_NEOHOOKE && p->dim != 3) return "NEOHOOKE needs dim 3";
     if (p->nlevels < 1 || p->nlevels > JFNK_MAX_LEVELS) return "nlevels out of range";
@@ -142,7 +142,7 @@ std::string validate(const jfnk_problem *p, const jfnk_options *o) {
     }
     long long nn = (long long)(p->n[0] + 1) * (p->n[1] + 1) * (p->dim == 3 ? p->n[2] + 1 : 1);
     if (nn > (1LL << 31) - 1) return "grid too large for 32-bit node indices";
-    if (p->kind == JFNK_PLAP && !(p->param[0] >= 1.0)) return "PLAP needs p >= 1";
+    if ((p->kind == JFNK_PLAP || p->kind == JFNK_PLAP_GAUSS) && !(p->param[0] >= 1.0)) return "PLAP needs p >= 1";
     if (p->kind == JFNK_NEOHOOKE && !(p->param[0] > 0.0 && p->param[1] > -1.0 && p->param[1] < 0.5))
         return "NEOHOOKE needs E > 0 and -1 < nu < 0.5";
     if (o->restart < 1 || o->restart > MAXR - 1) return "restart must be in [1, 31]";

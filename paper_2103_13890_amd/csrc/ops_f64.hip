@@ -48,6 +48,9 @@ void op_energy(const Exec &ex, const Grid &g, const Phys &ph, const double *u, d
     else if (ph.kind == JFNK_PLAP && g.dim == 2) k_energy<2, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
     else if (ph.kind == JFNK_PLAP) k_energy<3, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
     else if (ph.kind == JFNK_NEOHOOKE) k_energy<3, JFNK_NEOHOOKE><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
+    else if (ph.kind == JFNK_PLAP_GAUSS && g.dim == 2)
+        k_energy<2, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
+    else if (ph.kind == JFNK_PLAP_GAUSS) k_energy<3, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, u, ex.red, out);
     finish<1>(ex.st, ex.red, nb, FinStore<1>{out});
 }
 
@@ -132,6 +135,10 @@ void op_vjp(const Exec &ex, const Grid &g, const Phys &ph, const double *kap, co
         break;
     case JFNK_NEOHOOKE:
         k_vjp<3, JFNK_NEOHOOKE><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
+        break;
+    case JFNK_PLAP_GAUSS:
+        if (g.dim == 2) k_vjp<2, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
+        else k_vjp<3, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
         break;
     }
 }

@@ -7,7 +7,8 @@ from oracle.mg import MGOptions
 from oracle.problems import Problem
 from paper_2103_13890_amd import workloads as W
 
-PARAM_NAMES = {'bratu': ('lam',), 'plap': ('p', 'delta'), 'invcoef': (), 'neohooke': ('E', 'nu')}
+PARAM_NAMES = {'bratu': ('lam',), 'plap': ('p', 'delta'), 'plap_gauss': ('p', 'delta'), 'invcoef': (),
+               'neohooke': ('E', 'nu')}
 
 
 def oracle_problem(w):
@@ -68,6 +69,11 @@ def small(kind):
         return w
     if kind == 'plap':
         return W.scaled('plap3d-128', (36, 20, 12), nlevels=3, vcycle_prec=0, coarse_rtol=1e-6)
+    if kind == 'plap_gauss':
+        # the p-Laplacian with its coefficient at each Gauss point
+        w = W.scaled('plap3d-128', (36, 20, 12), nlevels=3, vcycle_prec=0, coarse_rtol=1e-6)
+        w.update(kind='plap_gauss')
+        return w
     if kind == 'minsurf':
         # the minimal-surface energy (p-Laplacian, p = 1, delta = 1) in 2D,
         # with the generic solver options of the small Bratu case

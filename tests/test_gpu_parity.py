@@ -27,7 +27,7 @@ from oracle import transfer as OT
 from paper_2103_13890_amd import api
 from paper_2103_13890_amd import workloads as W
 
-KINDS = ['bratu2d', 'bratu3d', 'plap', 'minsurf', 'invcoef', 'neohooke']
+KINDS = ['bratu2d', 'bratu3d', 'plap', 'plap_gauss', 'minsurf', 'invcoef', 'neohooke']
 
 
 def _inputs(w, seed, smooth=False):
@@ -120,17 +120,22 @@ def test_jv_f64(kind, path, form):
 TILE_CASES = [
     ('plap', (64, 17, 9), W.ALL3),
     ('plap', (64, 17, 9), [(0, 0), (1, 0), (2, 0)]),
+    ('plap_gauss', (64, 17, 9), W.ALL3),
+    ('plap_gauss', (128, 9, 5), [(0, 0), (1, 1), (2, 0)]),
     ('invcoef', (100, 19, 7), [(0, 1), (1, 1), (2, 0)]),
     ('bratu', (33, 9, 13), W.ALL3),
 ]
 
 
 def _tile_workload(kind, n, faces):
-    base = {'plap': 'plap3d-128', 'invcoef': 'invcoef3d-128', 'bratu': 'plap3d-128'}[kind]
+    base = {'plap': 'plap3d-128', 'plap_gauss': 'plap3d-128', 'invcoef': 'invcoef3d-128',
+            'bratu': 'plap3d-128'}[kind]
     w = W.scaled(base, n, nlevels=1, vcycle_prec=0)
     w['faces'] = faces
     if kind == 'bratu':
         w.update(kind='bratu', params=(2.0,))
+    if kind == 'plap_gauss':
+        w.update(kind='plap_gauss')
     return w
 
 
@@ -222,7 +227,7 @@ def _setup_both(w, u, m, **mg_over):
     return ctx, levels, opts
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'invcoef', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'plap_gauss', 'minsurf', 'invcoef', 'neohooke'])
 @pytest.mark.parametrize('form', [1, 2])
 def test_mg_setup(kind, form):
     w = small(kind)
@@ -237,7 +242,7 @@ def test_mg_setup(kind, form):
             assert rel(to_np(api.mg_get_level(ctx, l, 'eig')), lev.eig) < 1e-9
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'plap_gauss', 'minsurf', 'neohooke'])
 @pytest.mark.parametrize('form', [1, 2])
 def test_smoother(kind, form):
     w = small(kind)
@@ -285,7 +290,7 @@ def test_coarse_solve_spd_and_shift():
         assert rel(to_np(s), ref) < 1e-9
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'invcoef', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'plap_gauss', 'minsurf', 'invcoef', 'neohooke'])
 @pytest.mark.parametrize('form', [1, 2])
 def test_vcycle(kind, form):
     w = small(kind)
@@ -312,7 +317,7 @@ def test_vjp(kind):
         assert rel(to_np(gm), OD.vjp_coef(pb, g, u, v, m)) < 1e-12
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'minsurf', 'neohooke'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'plap_gauss', 'minsurf', 'neohooke'])
 def test_energy(kind):
     w = small(kind)
     ctx = make_ctx(w)

@@ -23,7 +23,7 @@ from paper_2103_13890_amd import workloads as W
 
 
 def _load(w):
-    if w['kind'] in ('plap', 'invcoef'):
+    if w['kind'] in ('plap', 'plap_gauss', 'invcoef'):
         c, wd, a = W.gaussian_params(1, 16, 3)
         return OP.load_from_function(oracle_grid(w), OP.gaussian_source(c, wd, a))
     if w['kind'] == 'neohooke':
@@ -40,7 +40,7 @@ def _oracle_solve(w, b, m=None, rtol=1e-12):
     return u, rep
 
 
-@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'neohooke-solve'])
+@pytest.mark.parametrize('kind', ['bratu2d', 'plap', 'plap_gauss', 'neohooke-solve'])
 def test_solution_parity_f64(kind):
     # the Neo-Hookean residual has a rounding floor near 1e-12 relative
     rtol = 1e-11 if kind.startswith('neohooke') else 1e-12

@@ -9,6 +9,11 @@
   t = sqrt(2 lam) cosh(t / 4) (lower root, found with scipy's brentq).
 * Neo-Hookean patch test: under a homogeneous deformation the stress is
   constant, so the residual vanishes at every interior node.
+* The Gauss-point p-Laplacian: for p = 2 both p-Laplacian residuals are the
+  exact Q1 stiffness (2^d Gauss points integrate it exactly), and on an
+  affine state the gradient is the same at every point, so the Gauss and
+  element-mean residuals agree there; elsewhere they differ.  Its 2D
+  manufactured solution converges at O(h^2).
 """
 import numpy as np
 import pytest
@@ -177,3 +182,41 @@ def test_bratu_1d_closed_form():
     r = _rates(errs)
     assert 3.8 < r[-1] < 4.2, (errs, r)
     assert errs[-1] < 1e-5
+
+
+@pytest.mark.parametrize('dim', [2, 3])
+def test_plap_gauss_reductions(dim):
+    rng = np.random.default_rng(21)
+    g = Grid([4] * dim, 0.25, ALL[dim])
+    zero = np.zeros(g.node_shape)
+    u = _rand_state(g, rng)
+    for prm in ({'p': 2.0, 'delta': 0.3}, {'p': 3.0, 'delta': 1e-2}):
+        Fg = apply_A(Problem('plap_gauss', prm), g, u)
+        Fm = apply_A(Problem('plap', prm), g, u)
+        if prm['p'] == 2.0:
+            assert np.max(np.abs(Fg - Fm)) < 1e-13
+        else:
+            assert np.max(np.abs(Fg - Fm)) > 1e-3
+    xs = g.node_coords()
+    aff = 0.2 + sum((0.5 - 0.3 * k) * x for k, x in enumerate(xs))
+    prm = {'p': 3.0, 'delta': 1e-2}
+    assert np.max(np.abs(apply_A(Problem('plap_gauss', prm), g, aff) - apply_A(Problem('plap', prm), g, aff))) < 1e-13
+    assert abs(energy(Problem('plap_gauss', prm), g, aff, zero) - energy(Problem('plap', prm), g, aff, zero)) < 1e-13
+
+
+def test_mms_plap_gauss_2d():
+    X = sympy.symbols('x y')
+    p, delta = 3, sympy.Rational(1, 10)
+    ue = sympy.sin(sympy.pi * X[0]) * sympy.sin(sympy.pi * X[1])
+    grad = [sympy.diff(ue, v) for v in X]
+    k = (delta ** 2 + sum(gi ** 2 for gi in grad)) ** sympy.Rational(p - 2, 2)
+    f = sympy.lambdify(X, -sum(sympy.diff(k * gi, v) for gi, v in zip(grad, X)), 'numpy')
+    uex = sympy.lambdify(X, ue, 'numpy')
+    pb = Problem('plap_gauss', {'p': float(p), 'delta': 0.1})
+    errs = []
+    for n in (16, 32, 64):
+        g = Grid([n] * 2, 1.0 / n, ALL[2])
+        u = _solve(pb, g, 2, load_from_function(g, f))
+        errs.append(np.max(np.abs(u - uex(*g.node_coords()))))
+    r = _rates(errs)
+    assert r[-1] > 3.5 and r[-1] < 4.6, (errs, r)
