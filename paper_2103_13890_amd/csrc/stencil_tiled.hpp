@@ -30,11 +30,14 @@ namespace jfnk {
 // despite the larger y halo); FP64: 4 for the plain FD quotient without
 // epilogue inputs (the outer J v: 166 VGPRs, 3 waves per SIMD, faster than
 // 6 rows at 2 waves), 3 for the residual (124 VGPRs, 4 waves per SIMD),
-// 4 otherwise.
-template <typename T, int MODE, class Epi> struct TileRows {
+// 4 otherwise.  The FP64 Gauss-point p-Laplacian takes 3 in every mode: 2
+// rows gain no register occupancy, 4 spill in the FD modes.
+constexpr int GAUSS_ROWS64 = 3;
+template <typename T, int MODE, class Epi, int KIND> struct TileRows {
     static constexpr bool jv64 = sizeof(T) == 8 && MODE == M_FD_PLAIN && Epi::NIN == 0;
     static constexpr bool res64 = sizeof(T) == 8 && MODE == M_RESID;
-    static constexpr int value = jv64 ? 4 : (res64 ? 3 : 4);
+    static constexpr bool gauss64 = sizeof(T) == 8 && KIND == JFNK_PLAP_GAUSS;
+    static constexpr int value = gauss64 ? GAUSS_ROWS64 : (jv64 ? 4 : (res64 ? 3 : 4));
 };
 constexpr int TMAX_THREADS = 512;   // nx <= 512 elements per row
 
@@ -52,11 +55,12 @@ __device__ __forceinline__ int xcd_tile(int id, int nb) {
 
 // Dynamic LDS of one block: two plane slots of x (T), e^m (T, INVCOEF) and
 // v (TV, FD modes), plus the (tile rows) x pitch hand-over buffer (T).
-template <typename T, typename TV, int MODE, class Epi, bool INV>
+template <typename T, typename TV, int MODE, class Epi, int KIND>
 inline size_t tiled_lds_bytes(int pitch, int srows) {
     constexpr bool FD = MODE != M_RESID;
+    constexpr bool INV = KIND == JFNK_INVCOEF;
     const size_t plane = (size_t)srows * pitch;
-    return 2 * plane * sizeof(T) * (INV ? 2 : 1) + (size_t)TileRows<T, MODE, Epi>::value * pitch * sizeof(T) +
+    return 2 * plane * sizeof(T) * (INV ? 2 : 1) + (size_t)TileRows<T, MODE, Epi, KIND>::value * pitch * sizeof(T) +
            (FD ? 2 * plane * sizeof(TV) : 0);
 }
 
@@ -66,7 +70,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                                                         const T *Ax, FdStep fd, Epi epi, Red red, TileArgs ta) {
     constexpr bool FD = MODE != M_RESID;
     constexpr bool INV = KIND == JFNK_INVCOEF;
-    constexpr int R = TileRows<T, MODE, Epi>::value;
+    constexpr int R = TileRows<T, MODE, Epi, KIND>::value;
     extern __shared__ __align__(16) unsigned char smem[];
     const int P = ta.pitch;
     const int plane = ta.srows * P;
