@@ -169,7 +169,7 @@ template <int DIM, typename T> __device__ __forceinline__ T gq_pair(const T *k, 
 }
 
 // PLAP_GAUSS element vector; c = m |e| / (2^d h^2) (= m h^(d-2) / 2^d)
-template <int DIM, typename T>
+template <int DIM, typename T, int PF>
 __device__ __forceinline__ void elem_plap_gauss(const T *w, const Phys &ph, T h, T *r, T m) {
     constexpr int NV = Cell<DIM>::NV, NH = NV / 2;
     T G[DIM][NH];
@@ -177,7 +177,7 @@ __device__ __forceinline__ void elem_plap_gauss(const T *w, const Phys &ph, T h,
     const T ih2 = T(1) / (h * h), d2 = T(ph.a1) * T(ph.a1);
     T k[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) k[q] = plap_pow<T>(d2 + gq_dot<DIM, T>(G, G, q) * ih2, ph.a0, 0);
+    for (int q = 0; q < NV; ++q) k[q] = plap_pow<T, PF>(d2 + gq_dot<DIM, T>(G, G, q) * ih2, ph.a0, 0);
     T F[DIM][NH];
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
@@ -266,7 +266,7 @@ __device__ __forceinline__ void elem_plap_gauss_vjp(const T *w, const T *lam, co
 template <int DIM, int KIND, typename T, int PF = 0>
 __device__ __forceinline__ void elem_scalar(const T *w, const T *kap, const Phys &ph, T h, T *r, T m = T(1)) {
     if constexpr (KIND == JFNK_PLAP_GAUSS) {
-        elem_plap_gauss<DIM, T>(w, ph, h, r, m);
+        elem_plap_gauss<DIM, T, PF>(w, ph, h, r, m);
         return;
     }
     constexpr int NV = Cell<DIM>::NV;

@@ -30,8 +30,10 @@ namespace jfnk {
 // despite the larger y halo); FP64: 4 for the plain FD quotient without
 // epilogue inputs (the outer J v: 166 VGPRs, 3 waves per SIMD, faster than
 // 6 rows at 2 waves), 3 for the residual (124 VGPRs, 4 waves per SIMD),
-// 4 otherwise.  The FP64 Gauss-point p-Laplacian takes 3 in every mode: 2
-// rows gain no register occupancy, 4 spill in the FD modes.
+// 4 otherwise.  The FP64 Gauss-point p-Laplacian takes 3 in every mode
+// (p = 3 instantiation: the residual at 136 VGPRs, 3 waves per SIMD, beats
+// 2 rows at 116 VGPRs and 4 waves, 346 against 379 us at 256^3; in the FD
+// modes 2 rows gain no occupancy and 4 spill).
 constexpr int GAUSS_ROWS64 = 3;
 template <typename T, int MODE, class Epi, int KIND> struct TileRows {
     static constexpr bool jv64 = sizeof(T) == 8 && MODE == M_FD_PLAIN && Epi::NIN == 0;
