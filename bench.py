@@ -300,8 +300,7 @@ def main():
                     help='only run a 1 GiB device copy (to scale HBM counters) and exit')
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
-        print('bench.py runs on exactly one GPU: this build has no multi-GPU path '
-              '(sharding is described in DESIGN.md)', file=sys.stderr)
+        print('bench.py runs on exactly one GPU: libjfnk has no multi-GPU path', file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()

@@ -124,7 +124,7 @@ def test_coarse_cg_indefinite_shift():
     lev = _level(pb, g, x)
     J, idx = assembled_jacobian(pb, g, x)
     ev = np.linalg.eigvalsh(J)
-    assert (ev < 0).sum() == 4                   # indefinite (survey check)
+    assert (ev < 0).sum() == 4                   # indefinite
     r0 = np.zeros(g.node_shape)
     r0[g.dof_mask()] = np.sin(np.arange(idx.size))
     st = Stats()
