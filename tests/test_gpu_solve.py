@@ -85,6 +85,19 @@ def test_fp32_vcycle_reaches_same_root():
     assert its[1] <= 2 * its[0] + 5, its
 
 
+def test_fp32_vcycle_gauss_kind():
+    # the Gauss-point p-Laplacian with FP32 levels (its FP32 difference-form
+    # kernels in the V-cycle) reaches the oracle's root as the FP64 solve does
+    w = small('plap_gauss')
+    b = _load(w)
+    ref, _ = _oracle_solve(w, b, rtol=1e-10)
+    ctx = make_ctx(w, vcycle_prec=1, coarse_rtol=1e-3, newton_rtol=1e-10)
+    u = to_dev(np.zeros_like(ref))
+    rep = api.jfnk_solve(ctx, u, None, to_dev(b))
+    assert rep['status'] == 'ok', rep
+    assert rel(to_np(u), ref) < 1e-7
+
+
 def test_invcoef_solve_and_gradient():
     w = W.scaled('invcoef3d-128', (16, 16, 16), nlevels=3)
     g = oracle_grid(w)
