@@ -5,6 +5,9 @@
 // rerun from the current correction while lambda_c < 0 (Sec. 2, coarse
 // level solver).  The whole loop runs on the device: one launch per coarse
 // solve, no host round trip.
+#include <map>
+#include <mutex>
+
 #include "stencil.hpp"
 #include "ops.hpp"
 
@@ -26,6 +29,111 @@ struct CgSum {
 };
 
 #define NODE_LOOP(i, n) for (long long i = threadIdx.x; i < (n); i += blockDim.x)
+
+// ---- CG-QN: the L-BFGS two-loop recursion in compact form -------------------
+// H r (Nocedal and Wright, Alg. 7.4, H_0 = gamma I) for the kept pairs
+// (s_k, y_k), oldest first, written with their Gram entries s_a.y_b (a < b)
+// and y_a.y_b: the first loop's coefficients are
+//   alpha_k = rho_k (s_k.r - sum_{j>k} alpha_j s_k.y_j),
+// the second loop's
+//   beta_k = rho_k (gamma (y_k.r - sum_j alpha_j y_k.y_j)
+//                   + sum_{j<k} (alpha_j - beta_j) s_j.y_k),
+// and H r = gamma (r - sum_k alpha_k y_k) + sum_k (alpha_k - beta_k) s_k.
+// The same terms as the two loops, summed in another order: an application
+// needs one batched reduction of the 2m products s_k.r, y_k.r instead of 2m
+// block sums in sequence.  The Gram entries are formed once, when the pairs
+// are kept, and stored after rho in the state.
+
+struct QnLds {
+    double scr[MAX_WAVES][2 * QN_MAX];   // wave totals of a batched sum
+    double tot[2 * QN_MAX];              // its block totals
+    double rho[QN_MAX], cs[QN_MAX], cy[QN_MAX];
+    double sy[QN_MAX * QN_MAX], yy[QN_MAX * QN_MAX];
+};
+
+// L.tot[k] = the block sum of v(k) for k < cnt <= 2 QN_MAX, each wave's part
+// by DPP and the waves in order; two barriers, all threads must call.
+template <class F> __device__ __forceinline__ void qn_sums(QnLds &L, int cnt, F v) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    for (int k = 0; k < cnt; ++k) {
+        const double w = wave_sum(v(k));
+        if (lane == 0) L.scr[wid][k] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += L.scr[w][threadIdx.x];
+        L.tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// Coefficients of H r from L.tot[2k] = s_k.r, L.tot[2k+1] = y_k.r, by the
+// first wave (lane k owns pair k; the recurrences broadcast each new
+// coefficient and update the open sums of the other lanes):
+// H r = gamma r + sum_k (cs_k s_k + cy_k y_k).
+__device__ __forceinline__ void qn_coeffs(QnLds &L, int np, double gam) {
+    const int l = threadIdx.x;
+    const bool on = l < np;
+    // first loop, k = np-1 .. 0: t_l = s_l.r - sum_{j>l} alpha_j s_l.y_j
+    double t = on ? L.tot[2 * l] : 0.0, al = 0.0;
+    for (int k = np - 1; k >= 0; --k) {
+        const double ak = L.rho[k] * __shfl(t, k);
+        if (l == k) al = ak;
+        if (on && l < k) t -= ak * L.sy[l * QN_MAX + k];
+    }
+    // y_l.q with q = r - sum_j alpha_j y_j
+    double yq = on ? L.tot[2 * l + 1] : 0.0;
+    for (int j = 0; j < np; ++j) {
+        const double aj = __shfl(al, j);
+        if (on) yq -= aj * L.yy[l * QN_MAX + j];
+    }
+    // second loop, k = 0 .. np-1: u_l = gamma y_l.q + sum_{j<l} (alpha_j - beta_j) s_j.y_l
+    double u = gam * yq, be = 0.0;
+    for (int k = 0; k < np; ++k) {
+        const double bk = L.rho[k] * __shfl(u, k);
+        const double dk = __shfl(al, k) - bk;
+        if (l == k) be = bk;
+        if (on && l > k) u += dk * L.sy[k * QN_MAX + l];
+    }
+    if (on) {
+        L.cs[l] = al - be;
+        L.cy[l] = -gam * al;
+    }
+}
+
+// Load rho and the Gram entries of np kept pairs from the state into LDS.
+__device__ __forceinline__ void qn_load(QnLds &L, const double *st, int np) {
+    if ((int)threadIdx.x < np) L.rho[threadIdx.x] = st[3 + threadIdx.x];
+    for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
+        const int a = t / np, b = t % np;
+        L.sy[a * QN_MAX + b] = st[QN_OFF_SY + a * QN_MAX + b];
+        L.yy[a * QN_MAX + b] = st[QN_OFF_YY + a * QN_MAX + b];
+    }
+}
+
+// Gram entries of the np pairs just kept, to LDS and the state; dot(k, a, b)
+// returns this thread's part of y_a.y_b (k = 0) or s_a.y_b (k = 1).
+template <class D> __device__ __forceinline__ void qn_gram(QnLds &L, double *st, int np, D dot) {
+    for (int a = 0; a < np; ++a) {
+        const int cnt = 2 * (np - a);
+        qn_sums(L, cnt, [&](int k) -> double { return dot(k & 1, a, a + (k >> 1)); });
+        if ((int)threadIdx.x < cnt) {
+            const int b = a + ((int)threadIdx.x >> 1);
+            const double v = L.tot[threadIdx.x];
+            if (threadIdx.x & 1) {
+                L.sy[a * QN_MAX + b] = v;
+                st[QN_OFF_SY + a * QN_MAX + b] = v;
+            } else {
+                L.yy[a * QN_MAX + b] = v;
+                L.yy[b * QN_MAX + a] = v;
+                st[QN_OFF_YY + a * QN_MAX + b] = v;
+                st[QN_OFF_YY + b * QN_MAX + a] = v;
+            }
+        }
+    }
+    __syncthreads();
+}
 
 template <int DIM, int KIND, int MODE, typename T>
 __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap, const T *x, const T *Ax,
@@ -119,32 +227,28 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
     // is touched by the thread that owns entry k of every vector)
     T *rec_s = (T *)ca.qn_rec, *rec_y = rec_s ? rec_s + (size_t)ca.qn_cap * n : nullptr;
     T *ps = (T *)ca.qn_pairs, *py = ps ? ps + (size_t)ca.qn_m * n : nullptr;
-    __shared__ double srho[QN_MAX], sa[QN_MAX];
+    __shared__ QnLds L;
     const bool qn_on = ca.qn_m > 0;
     bool recording = qn_on && ca.qn_state[0] == 0.0;
     int np = (qn_on && !recording) ? (int)ca.qn_state[1] : 0;
     double gam = np > 0 ? ca.qn_state[2] : 1.0;
-    if (threadIdx.x < np) srho[threadIdx.x] = ca.qn_state[3 + threadIdx.x];
+    if (np > 0) qn_load(L, ca.qn_state, np);
     __syncthreads();
     int nrec = 0;
-    // z = H r by the two-loop recursion (np > 0)
+    // z = H r by the compact recursion (np > 0)
     auto prec = [&]() __attribute__((always_inline)) {
-        NODE_LOOP(i, n) z[i] = r[i];
-        for (int k = np - 1; k >= 0; --k) {
-            const T *sk = ps + (size_t)k * n, *yk = py + (size_t)k * n;
+        qn_sums(L, 2 * np, [&](int k) -> double {
+            const T *w = ((k & 1) ? py : ps) + (size_t)(k >> 1) * n;
             double d = 0.0;
-            NODE_LOOP(i, n) d += (double)sk[i] * (double)z[i];
-            const double ak = srho[k] * cg_bsum(d);
-            if (threadIdx.x == 0) sa[k] = ak;
-            NODE_LOOP(i, n) z[i] -= (T)ak * yk[i];
-        }
-        NODE_LOOP(i, n) z[i] = (T)gam * z[i];
-        for (int k = 0; k < np; ++k) {
-            const T *sk = ps + (size_t)k * n, *yk = py + (size_t)k * n;
-            double d = 0.0;
-            NODE_LOOP(i, n) d += (double)yk[i] * (double)z[i];
-            const double bk = srho[k] * cg_bsum(d);
-            NODE_LOOP(i, n) z[i] += (T)(sa[k] - bk) * sk[i];
+            NODE_LOOP(i, n) d += (double)w[i] * (double)r[i];
+            return d;
+        });
+        if (threadIdx.x < 64) qn_coeffs(L, np, gam);
+        __syncthreads();
+        NODE_LOOP(i, n) {
+            T zi = (T)gam * r[i];
+            for (int k = 0; k < np; ++k) zi += (T)L.cs[k] * ps[(size_t)k * n + i] + (T)L.cy[k] * py[(size_t)k * n + i];
+            z[i] = zi;
         }
     };
 
@@ -257,7 +361,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
                 const double yy = cg_bsum(d2);
                 if (threadIdx.x == 0) {
                     ca.qn_state[3 + kept] = 1.0 / sy;
-                    srho[kept] = 1.0 / sy;
+                    L.rho[kept] = 1.0 / sy;
                 }
                 g_s = sy / yy;
                 ++kept;
@@ -270,6 +374,12 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
         }
         __threadfence_block();
         __syncthreads();
+        qn_gram(L, ca.qn_state, kept, [&](int sy, int a, int b) -> double {
+            const T *u = (sy ? ps : py) + (size_t)a * n, *w = py + (size_t)b * n;
+            double d = 0.0;
+            NODE_LOOP(i, n) d += (double)u[i] * (double)w[i];
+            return d;
+        });
         np = kept;
         gam = kept > 0 ? g_s : 1.0;
         recording = false;
@@ -381,33 +491,31 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
 
     // L-BFGS preconditioner (CG-QN): the first solve with no pairs records
     // every step of its first CG; pairs kept afterwards precondition all CG
-    // runs (two-loop recursion, H_0 = gamma I of the newest pair)
+    // runs (the compact two-loop recursion, H_0 = gamma I of the newest
+    // pair).  Each lane touches only its own node's pair entries; the
+    // coefficients and Gram entries live in LDS.
     T *rec_s = (T *)ca.qn_rec, *rec_y = rec_s ? rec_s + (size_t)ca.qn_cap * nn : nullptr;
     T *ps = (T *)ca.qn_pairs, *py = ps ? ps + (size_t)ca.qn_m * nn : nullptr;
-    // rho_k and the first-loop coefficients live in LDS (the same value in
-    // every lane); each lane touches only its own node's pair entries
-    __shared__ double srho[QN_MAX], sa[QN_MAX];
+    __shared__ QnLds L;
     const bool qn_on = ca.qn_m > 0;
     bool recording = qn_on && ca.qn_state[0] == 0.0;
     int np = (qn_on && !recording) ? (int)ca.qn_state[1] : 0;
     double gam = np > 0 ? ca.qn_state[2] : 1.0;
-    if (threadIdx.x < np) srho[threadIdx.x] = ca.qn_state[3 + threadIdx.x];
+    if (np > 0) qn_load(L, ca.qn_state, np);
     __syncthreads();
     int nrec = 0;
     auto prec = [&](T r) __attribute__((always_inline)) -> T {
         if (np == 0) return r;
-        T q = r;
-        for (int k = np - 1; k >= 0; --k) {
-            const T sk = act ? ps[(size_t)k * nn + i] : T(0), yk = act ? py[(size_t)k * nn + i] : T(0);
-            const double ak = srho[k] * cg_bsum((double)sk * (double)q);
-            if (threadIdx.x == 0) sa[k] = ak;
-            q -= (T)ak * yk;
-        }
-        T z = (T)gam * q;
+        qn_sums(L, 2 * np, [&](int k) -> double {
+            const T w = act ? ((k & 1) ? py : ps)[(size_t)(k >> 1) * nn + i] : T(0);
+            return (double)w * (double)r;
+        });
+        if (threadIdx.x < 64) qn_coeffs(L, np, gam);
+        __syncthreads();
+        T z = (T)gam * r;
         for (int k = 0; k < np; ++k) {
             const T sk = act ? ps[(size_t)k * nn + i] : T(0), yk = act ? py[(size_t)k * nn + i] : T(0);
-            const double bk = srho[k] * cg_bsum((double)yk * (double)z);
-            z += (T)(sa[k] - bk) * sk;
+            z += (T)L.cs[k] * sk + (T)L.cy[k] * yk;
         }
         return z;
     };
@@ -476,7 +584,7 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
                 }
                 if (threadIdx.x == 0) {
                     ca.qn_state[3 + kept] = 1.0 / sy;
-                    srho[kept] = 1.0 / sy;
+                    L.rho[kept] = 1.0 / sy;
                 }
                 g_s = sy / yy;
                 ++kept;
@@ -487,9 +595,12 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse_small(Grid g, Phys ph, const 
             ca.qn_state[1] = (double)kept;
             ca.qn_state[2] = kept > 0 ? g_s : 1.0;
         }
-        // the pairs written above are read back by other lanes in prec()
         __threadfence_block();
         __syncthreads();
+        qn_gram(L, ca.qn_state, kept, [&](int sy, int a, int b) -> double {
+            if (!act) return 0.0;
+            return (double)(sy ? ps : py)[(size_t)a * nn + i] * (double)py[(size_t)b * nn + i];
+        });
         np = kept;
         gam = kept > 0 ? g_s : 1.0;
         recording = false;
@@ -534,17 +645,46 @@ size_t coarse_work_elems(const Grid &g, int nc) {
     return (size_t)(4 * g.nn * nc + (g.dim == 3 ? 8 : 4) * ne * nc);
 }
 
+// The small kernel's static LDS (the CG-QN arrays) plus up to 64 KB of
+// dynamic LDS can pass the default 64 KB per workgroup: raise its dynamic
+// limit once per device; if the runtime refuses, the generic kernel runs.
+static bool coarse_lds_ok(const void *fn, size_t dyn) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, bool> ok;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dev, fn);
+    auto it = ok.find(key);
+    if (it == ok.end()) {
+        const bool r = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024) == hipSuccess;
+        if (!r) (void)hipGetLastError();
+        it = ok.emplace(key, r).first;
+    }
+    return it->second && dyn <= 64 * 1024;
+}
+
 template <int DIM, int KIND, typename T>
 static void launch_coarse(const Exec &ex, int mode, const Grid &g, const Phys &ph, const T *kap, const T *x,
                           const T *Ax, const double *num, const T *b, T *s, T *work, const CoarseArgs &ca) {
     if constexpr (KIND != JFNK_NEOHOOKE) {
         const size_t lds = coarse_small_lds(g, KIND, sizeof(T));
         if (coarse_small(g, KIND, sizeof(T))) {
-            if (mode == M_FD_DIFF)
-                k_coarse_small<DIM, KIND, M_FD_DIFF, T><<<1, CBLOCK, lds, ex.st>>>(g, ph, kap, x, Ax, num, b, s, ca);
-            else
-                k_coarse_small<DIM, KIND, M_FD_PLAIN, T><<<1, CBLOCK, lds, ex.st>>>(g, ph, kap, x, Ax, num, b, s, ca);
-            return;
+            if (mode == M_FD_DIFF) {
+                const void *fn = (const void *)k_coarse_small<DIM, KIND, M_FD_DIFF, T>;
+                if (coarse_lds_ok(fn, lds)) {
+                    k_coarse_small<DIM, KIND, M_FD_DIFF, T><<<1, CBLOCK, lds, ex.st>>>(g, ph, kap, x, Ax, num, b, s,
+                                                                                      ca);
+                    return;
+                }
+            } else {
+                const void *fn = (const void *)k_coarse_small<DIM, KIND, M_FD_PLAIN, T>;
+                if (coarse_lds_ok(fn, lds)) {
+                    k_coarse_small<DIM, KIND, M_FD_PLAIN, T><<<1, CBLOCK, lds, ex.st>>>(g, ph, kap, x, Ax, num, b,
+                                                                                       s, ca);
+                    return;
+                }
+            }
         }
     }
     if (mode == M_FD_DIFF)

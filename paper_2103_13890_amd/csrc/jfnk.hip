@@ -204,7 +204,7 @@ void plan(jfnk_ctx *c, Carve &cv) {
         c->qn_cap = c->opt.coarse_maxit > 0 ? c->opt.coarse_maxit : (int)level_dofs(g0, nc);
         c->qn_rec = cv.take(2 * (size_t)c->qn_cap * vb0);
         c->qn_pairs = cv.take(2 * (size_t)c->opt.coarse_qn * vb0);
-        c->qn_state = (double *)cv.take(64 * sizeof(double));
+        c->qn_state = (double *)cv.take(QN_STATE_LEN * sizeof(double));
     }
     const Grid gf = level_grid(c->prob, c->prob.nlevels - 1);
     c->nn = gf.nn;

@@ -180,6 +180,11 @@ void tr_prolong_add(const Exec &, const Grid &fine, const Grid &coarse, int nc, 
 
 // ---- coarse solve (Algorithm 1, level 0) ------------------------------------------
 constexpr int QN_MAX = 32;   // secant pairs of the coarse L-BFGS preconditioner
+// qn_state layout: [0] 0 none / 1 built, [1] pairs kept, [2] gamma,
+// [3 + i] 1/(s_i.y_i), then s_a.y_b and y_a.y_b ([a][b], QN_MAX columns)
+constexpr int QN_OFF_SY = 3 + QN_MAX;
+constexpr int QN_OFF_YY = QN_OFF_SY + QN_MAX * QN_MAX;
+constexpr int QN_STATE_LEN = QN_OFF_YY + QN_MAX * QN_MAX;
 struct CoarseArgs {
     int maxit, shift_max;
     double atol, rtol, gamma;
@@ -187,8 +192,8 @@ struct CoarseArgs {
                         // [4] negative-curvature exits (accumulated over calls)
     // L-BFGS preconditioner (CG-QN), qn_m > 0 pairs: the first call records
     // every CG step's pair into qn_rec ([2][qn_cap][nn], level precision)
-    // and keeps a uniform sample in qn_pairs ([2][qn_m][nn]); qn_state:
-    // [0] 0 none / 1 built, [1] pairs kept, [2] gamma, [3 + i] 1/(s_i.y_i)
+    // and keeps a uniform sample in qn_pairs ([2][qn_m][nn]); qn_state
+    // (QN_STATE_LEN doubles) as laid out above
     int qn_m = 0, qn_cap = 0;
     void *qn_rec = nullptr, *qn_pairs = nullptr;
     double *qn_state = nullptr;
