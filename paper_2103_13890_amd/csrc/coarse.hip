@@ -156,7 +156,67 @@ __global__ __launch_bounds__(CBLOCK) void k_coarse(Grid g, Phys ph, const T *kap
         const double eps = vv > 0.0 ? epsn / sqrt(vv) : 0.0;
         const T e = (T)eps;
         const bool zero_fd = eps == 0.0;
-        NODE_LOOP(el, ne) {
+        if constexpr (KIND == JFNK_NEOHOOKE) {
+            // eight lanes per element, one per Gauss point, summed by a fixed
+            // butterfly; every lane runs the same rounds (wave-uniform exchanges)
+            const long long tot = ne * 8;
+            const long long rounds = (tot + blockDim.x - 1) / blockDim.x;
+            for (long long k = 0; k < rounds; ++k) {
+                const long long t = threadIdx.x + k * blockDim.x;
+                const bool live = t < tot && !zero_fd;
+                const long long el = t < tot ? (t >> 3) : 0;
+                const int gq = (int)(t & 7);
+                T r8[NC][NV];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int a = 0; a < NV; ++a) r8[c][a] = T(0);
+                if (live) {
+                    unsigned qq, rr, q2, r2;
+                    udivmod((unsigned)el, (unsigned)g.nx, rnx, qq, rr);
+                    udivmod(qq, (unsigned)g.ny, rny, q2, r2);
+                    const int ex = (int)rr, ey = (int)r2, ez = (int)q2;
+                    T xe[NC][NV], ve[NC][NV];
+#pragma unroll
+                    for (int a = 0; a < NV; ++a) {
+                        const int ax = ex + (a & 1), ay = ey + ((a >> 1) & 1), az = ez + ((a >> 2) & 1);
+                        const long long j = node_index(g, ax, ay, az);
+                        const bool dj = is_dirichlet(g, ax, ay, az);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            xe[c][a] = x[c * nn + j];
+                            ve[c][a] = dj ? T(0) : v[c * nn + j];
+                        }
+                    }
+                    if constexpr (MODE == M_FD_DIFF) {
+                        nh_point_fd<T>(xe, ve, e, ph, h, gq, r8);
+                    } else {
+                        T w[NC][NV];
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+#pragma unroll
+                            for (int a = 0; a < NV; ++a) w[c][a] = xe[c][a] + e * ve[c][a];
+                        nh_point<T>(w, ph, h, gq, r8);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int a = 0; a < NV; ++a) {
+                        T val = r8[c][a];
+                        val += __shfl_xor(val, 1);
+                        val += __shfl_xor(val, 2);
+                        val += __shfl_xor(val, 4);
+                        r8[c][a] = val;
+                    }
+                if (t < tot && gq == 0) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+#pragma unroll
+                        for (int a = 0; a < NV; ++a) ew[(c * ne + el) * NV + a] = zero_fd ? T(0) : r8[c][a];
+                }
+            }
+        } else NODE_LOOP(el, ne) {
             unsigned qq, rr, q2, r2;
             udivmod((unsigned)el, (unsigned)g.nx, rnx, qq, rr);
             udivmod(qq, (unsigned)g.ny, rny, q2, r2);

@@ -574,16 +574,13 @@ __device__ __forceinline__ T nh_cof(const T F[3][3], T C[3][3]) {
     return F[0][0] * C[0][0] + F[0][1] * C[0][1] + F[0][2] * C[0][2];
 }
 
+// Gauss point q's part of the element vector, added to r
 template <typename T>
-__device__ __forceinline__ void elem_neohooke(const T (*w)[8], const Phys &ph, T h, T (*r)[8]) {
+__device__ __forceinline__ void nh_point(const T (*w)[8], const Phys &ph, T h, int q, T (*r)[8]) {
     const T mu = T(ph.a0), lam = T(ph.a1);
     const T wq = h * h * h / T(8);
     const T ih = T(1) / h;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int a = 0; a < 8; ++a) r[i][a] = T(0);
-    for (int q = 0; q < 8; ++q) {
+    {
         T F[3][3], C[3][3];
         nh_grad<T>(w, q, h, F);
         T J = nh_cof<T>(F, C);
@@ -604,6 +601,15 @@ __device__ __forceinline__ void elem_neohooke(const T (*w)[8], const Phys &ph, T
             for (int i = 0; i < 3; ++i) r[i][a] += P[i][0] * d0 + P[i][1] * d1 + P[i][2] * d2;
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void elem_neohooke(const T (*w)[8], const Phys &ph, T h, T (*r)[8]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) r[i][a] = T(0);
+    for (int q = 0; q < 8; ++q) nh_point<T>(w, ph, h, q, r);
 }
 
 template <typename T>
@@ -633,17 +639,14 @@ __device__ __forceinline__ T elem_neohooke_energy(const T (*w)[8], const Phys &p
 //   J_w - J_x = eps tr(adj(F_x) G) + eps^2 tr(F_x adj(G)) + eps^3 det G
 //   (P_w - P_x)/eps = mu G + (mu - lam ln J_x) F_w^-T G^T F_x^-T
 //                     + lam log1p((J_w - J_x)/J_x)/eps F_w^-T
+// Gauss point q's part, added to r
 template <typename T>
-__device__ __forceinline__ void elem_neohooke_fd(const T (*x)[8], const T (*v)[8], T eps, const Phys &ph, T h,
-                                                 T (*r)[8]) {
+__device__ __forceinline__ void nh_point_fd(const T (*x)[8], const T (*v)[8], T eps, const Phys &ph, T h, int q,
+                                            T (*r)[8]) {
     const T mu = T(ph.a0), lam = T(ph.a1);
     const T wq = h * h * h / T(8);
     const T ih = T(1) / h;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int a = 0; a < 8; ++a) r[i][a] = T(0);
-    for (int q = 0; q < 8; ++q) {
+    {
         T F[3][3], C[3][3], G[3][3], Cg[3][3];
         nh_grad<T>(x, q, h, F);
         nh_grad<T>(v, q, h, G, false);
@@ -692,6 +695,16 @@ __device__ __forceinline__ void elem_neohooke_fd(const T (*x)[8], const T (*v)[8
             for (int i = 0; i < 3; ++i) r[i][a] += P[i][0] * d0 + P[i][1] * d1 + P[i][2] * d2;
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void elem_neohooke_fd(const T (*x)[8], const T (*v)[8], T eps, const Phys &ph, T h,
+                                                 T (*r)[8]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) r[i][a] = T(0);
+    for (int q = 0; q < 8; ++q) nh_point_fd<T>(x, v, eps, ph, h, q, r);
 }
 
 // dP = mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam tr(F^-1 dF) F^-T ; r = sum_q w_q dP grad phi
