@@ -153,8 +153,9 @@ typedef struct {
      * V-cycle per step; JFNK_OUTER_CG the paper's CG-MG: conjugate gradients
      * preconditioned by one V-cycle per step, at most restart * max_cycles
      * steps, stopped at ||r|| <= eta ||F|| or at a direction p with
-     * p.Jp <= 0 (the step so far is kept).  jfnk_adjoint_solve always uses
-     * FGMRES. */
+     * p.Jp <= 0 (the step so far is kept).  CG assumes a symmetric J: it
+     * is meant for the variational kinds, not JFNK_INVCOEF.
+     * jfnk_adjoint_solve always uses FGMRES. */
     int outer_krylov;
 } jfnk_options;
 
