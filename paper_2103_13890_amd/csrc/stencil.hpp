@@ -454,4 +454,87 @@ __global__ __launch_bounds__(BLOCK) void k_node(Grid g, Phys ph, const T *kap, c
     if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
 }
 
+// Node values of the Neo-Hookean kind with one wavefront per node: lane l
+// evaluates Gauss point l & 7 of element l >> 3 around the node (the
+// element whose corner l >> 3 the node is), and the wave sums the 64 parts
+// by DPP in a fixed order.  A node's 8 elements x 8 points run in parallel
+// instead of in one lane's sequence, which bounded every level of the
+// node-centric Neo-Hookean hierarchy by one thread's latency.  Every lane of
+// a wave walks the same nodes, so the sums are wave-uniform; lane 0 applies
+// the epilogue.
+template <int MODE, typename T, typename TV, class Epi>
+__global__ __launch_bounds__(BLOCK) void k_node_nh(Grid g, Phys ph, const T *x, const TV *v, const T *Ax,
+                                                   FdStep fd, Epi epi, Red red) {
+    constexpr int NC = 3;
+    const double eps = fd_eps_prepare(fd, epi);
+    double sums[Epi::NS > 0 ? Epi::NS : 1];
+#pragma unroll
+    for (int k = 0; k < (Epi::NS > 0 ? Epi::NS : 1); ++k) sums[k] = 0.0;
+    const long long nn = g.nn;
+    const int lane = threadIdx.x & 63;
+    const int el = lane >> 3, gq = lane & 7;
+    const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long long nwaves = ((long long)gridDim.x * blockDim.x) >> 6;
+    const T h = (T)g.h, e = (T)eps;
+    for (long long i = wave; i < nn; i += nwaves) {
+        int X, Y, Z;
+        node_coords(g, i, X, Y, Z);
+        const bool dir = is_dirichlet(g, X, Y, Z);
+        const bool eval = !dir && !(MODE != M_RESID && eps == 0.0);
+        const int ex = X - (el & 1), ey = Y - ((el >> 1) & 1), ez = Z - ((el >> 2) & 1);
+        const bool inside = eval && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny && ez >= 0 && ez < g.nz;
+        T c3[NC] = {T(0), T(0), T(0)};
+        if (inside) {
+            T xe[NC][8], ve[NC][8], r8[NC][8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int ax = ex + (a & 1), ay = ey + ((a >> 1) & 1), az = ez + ((a >> 2) & 1);
+                const long long j = node_index(g, ax, ay, az);
+                const bool dj = (MODE != M_RESID) && is_dirichlet(g, ax, ay, az);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    xe[c][a] = x[c * nn + j];
+                    ve[c][a] = (MODE == M_RESID || dj) ? T(0) : (T)v[c * nn + j];
+                    r8[c][a] = T(0);
+                }
+            }
+            if constexpr (MODE == M_FD_DIFF) {
+                nh_point_fd<T>(xe, ve, e, ph, h, gq, r8);
+            } else if constexpr (MODE == M_FD_PLAIN) {
+                T w[NC][8];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int a = 0; a < 8; ++a) w[c][a] = xe[c][a] + e * ve[c][a];
+                nh_point<T>(w, ph, h, gq, r8);
+            } else {
+                nh_point<T>(xe, ph, h, gq, r8);
+            }
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                if (a == el) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) c3[c] = r8[c][a];
+                }
+        }
+        T val[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) val[c] = (T)wave_sum((double)c3[c]);
+        if (lane == 0) {
+            if constexpr (MODE == M_FD_PLAIN) {
+                if (eval) {
+                    const T ie = (T)(1.0 / eps);
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) val[c] = (val[c] - Ax[c * nn + i]) * ie;
+                }
+            }
+            T in[Epi::NIN * NC > 0 ? Epi::NIN * NC : 1];
+            const PtrAt at{i};
+            epi.load(at, in);
+            epi.node(at, val, dir, sums, in);
+        }
+    }
+    if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
+}
+
 }  // namespace jfnk
