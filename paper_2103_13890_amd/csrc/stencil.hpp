@@ -454,6 +454,83 @@ __global__ __launch_bounds__(BLOCK) void k_node(Grid g, Phys ph, const T *kap, c
     if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
 }
 
+// Contribution to node (X, Y, Z) of element el around it (the element whose
+// corner el the node is), for the scalar kinds; 0 outside the grid.
+template <int DIM, int KIND, int MODE, typename T, typename TV>
+__device__ __forceinline__ T node_elem_scalar(const Grid &g, const Phys &ph, const T *kap, const T *x, const TV *v,
+                                              double eps, int X, int Y, int Z, int el) {
+    constexpr int NV = Cell<DIM>::NV;
+    constexpr bool FD = MODE != M_RESID;
+    constexpr bool INV = KIND == JFNK_INVCOEF;
+    const int ex = X - (el & 1), ey = Y - ((el >> 1) & 1), ez = DIM == 3 ? Z - ((el >> 2) & 1) : 0;
+    if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny) return T(0);
+    if (DIM == 3 && (ez < 0 || ez >= g.nz)) return T(0);
+    T xe[1][NV], ve[1][NV], kp[NV], r[1][NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        const int ax = ex + (a & 1), ay = ey + ((a >> 1) & 1), az = ez + ((a >> 2) & 1);
+        const long long j = node_index(g, ax, ay, az);
+        xe[0][a] = x[j];
+        ve[0][a] = (FD && !is_dirichlet(g, ax, ay, az)) ? (T)v[j] : T(0);
+        kp[a] = INV ? kap[j] : T(0);
+    }
+    elem_eval<DIM, KIND, MODE, T, 1, NV>(xe, ve, kp, (T)eps, ph, (T)g.h, r);
+    T out = T(0);
+#pragma unroll
+    for (int a = 0; a < NV; ++a)
+        if (a == el) out = r[0][a];
+    return out;
+}
+
+// Node-centric evaluation for the scalar kinds on small levels with 2^d
+// lanes per node: lane el of a node's group evaluates element el around
+// it, and the group sums the contributions by a fixed butterfly, so a
+// node's 2^d element evaluations run in parallel (on small levels one
+// thread's chain of them bounds the launch).  Every lane runs the same
+// number of rounds, so the exchanges are wave-uniform; lane 0 of a group
+// applies the epilogue.
+template <int DIM, int KIND, int MODE, typename T, typename TV, class Epi>
+__global__ __launch_bounds__(BLOCK) void k_node_split(Grid g, Phys ph, const T *kap, const T *x, const TV *v,
+                                                      const T *Ax, FdStep fd, Epi epi, Red red) {
+    constexpr int NV = Cell<DIM>::NV;
+    static_assert(BLOCK % NV == 0, "a node's lanes share one block");
+    const double eps = fd_eps_prepare(fd, epi);
+    double sums[Epi::NS > 0 ? Epi::NS : 1];
+#pragma unroll
+    for (int k = 0; k < (Epi::NS > 0 ? Epi::NS : 1); ++k) sums[k] = 0.0;
+    const long long total = g.nn * NV;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long rounds = (total + stride - 1) / stride;
+    const int el = threadIdx.x & (NV - 1);
+    for (long long k = 0; k < rounds; ++k) {
+        const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x + k * stride;
+        const bool live = t < total;
+        const long long i = live ? t / NV : 0;
+        int X = 0, Y = 0, Z = 0;
+        bool dir = true;
+        if (live) {
+            node_coords(g, i, X, Y, Z);
+            dir = is_dirichlet(g, X, Y, Z);
+        }
+        const bool eval = live && !dir && !(MODE != M_RESID && eps == 0.0);
+        T c = T(0);
+        if (eval) c = node_elem_scalar<DIM, KIND, MODE, T, TV>(g, ph, kap, x, v, eps, X, Y, Z, el);
+#pragma unroll
+        for (int o = 1; o < NV; o <<= 1) c += __shfl_xor(c, o);
+        if (live && el == 0) {
+            T val[1] = {c};
+            if constexpr (MODE == M_FD_PLAIN) {
+                if (eval) val[0] = (val[0] - Ax[i]) * (T)(1.0 / eps);
+            }
+            T in[Epi::NIN > 0 ? Epi::NIN : 1];
+            const PtrAt at{i};
+            epi.load(at, in);
+            epi.node(at, val, dir, sums, in);
+        }
+    }
+    if constexpr (Epi::NS > 0) block_partials<Epi::NS>(sums, red);
+}
+
 // Node values of the Neo-Hookean kind with one wavefront per node: lane l
 // evaluates Gauss point l & 7 of element l >> 3 around the node (the
 // element whose corner l >> 3 the node is), and the wave sums the 64 parts
