@@ -11,9 +11,10 @@ SplitMix64 sequence whose state starts at seed + l * 2^32, i.e.
     z = (z ^ (z >> 27)) * 0x94D049BB133111EB
     z =  z ^ (z >> 31)
 
-mapped to [-1, 1) as (z >> 11) * 2^-52 - 1.  Parity unpinned against a
-published output table (none is printed with the definition); the GPU side
-implements the same definition independently and tests compare the two.
+mapped to [-1, 1) as (z >> 11) * 2^-52 - 1.  Pinned against the
+generator's known first outputs from state 0 (tests/test_oracle_rng.py);
+the GPU side implements the same definition independently and tests
+compare the two.
 """
 import numpy as np
 
