@@ -18,7 +18,8 @@ NumPy oracle on the host (see --help).  The paper's own experiments (Bratu
 and minimal surface on 800 x 800 elements, the Neo-Hookean beam on
 160 x 16 x 16, with its solver settings: CG-MG, V(5, 5), shifted coarse
 CG-QN, ||F|| <= 1e-6) are solved as well and reported beside the paper's
-Table 1-3 counts (--no-paper skips them).
+Table 1-3 counts, with Bratu and the minimal surface also at every
+refinement level L1..L5 (Table 2; --no-paper skips all of them).
 """
 import argparse
 import json
@@ -269,6 +270,38 @@ def paper_mode_solves(steps):
     return out
 
 
+# Table 2 (the paper's triangles): Newton and CG-MG steps per refinement
+# level L1..L5 for Bratu and the minimal surface
+PAPER_TABLE2 = {'bratu2d-800': [(3, 7), (3, 9), (3, 9), (3, 9), (3, 9)],
+                'minsurf2d-800': [(6, 13), (7, 18), (8, 25), (9, 32), (9, 41)]}
+
+
+def paper_levels():
+    """Table 2's trend on Q1 grids: Bratu and the minimal surface at L1..L5
+    (25 * 2^k elements per axis on k + 1 levels) with the paper's settings,
+    one untimed solve each."""
+    import torch
+    from paper_2103_13890_amd import api
+    from paper_2103_13890_amd import workloads as W
+    out = {}
+    for name in ('bratu2d-800', 'minsurf2d-800'):
+        rows = []
+        for k in range(1, 6):
+            w = W.scaled(name, (25 << k, 25 << k), nlevels=k + 1)
+            ctx = api.Context(build_problem(w), api.default_options(**w['options']))
+            u = torch.from_numpy(W.dirichlet_state(w)).to('cuda')
+            rep = api.jfnk_solve(ctx, u, None, torch.zeros_like(u))
+            p_in, p_cg = PAPER_TABLE2[name][k - 1]
+            rows.append({'level': f'L{k}', 'ok': rep['status'] == 'ok', 'newton': rep['newton_iters'],
+                         'cg_mg': rep['linear_iters'], 'ge_effective': rep['ge_effective'],
+                         'paper_newton': p_in, 'paper_cg_mg': p_cg})
+            del ctx
+        out[name] = rows
+        log(f'{name} L1..L5: Newton {[r["newton"] for r in rows]}, CG-MG {[r["cg_mg"] for r in rows]}, '
+            f'GE {[round(r["ge_effective"], 1) for r in rows]}')
+    return out
+
+
 def copy_calibration(nbytes=1 << 30, launches=5):
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -413,6 +446,7 @@ def main():
             f'{fg["tflops_fp64"]:.1f} TFLOP/s FP64')
     if not args.no_paper:
         extra['paper_settings'] = paper_mode_solves(max(1, min(args.steps, 3)))
+        extra['paper_table2_levels'] = paper_levels()
     cpu = None
     if not args.no_cpu:
         ge_ref = extra.get('fp64_mg', {}).get('ge_effective', ge32)
