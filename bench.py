@@ -270,24 +270,26 @@ def paper_mode_solves(steps):
     return out
 
 
-# Table 2 (the paper's triangles): Newton and CG-MG steps per refinement
-# level L1..L5 for Bratu and the minimal surface
+# Table 2 (the paper's meshes): Newton and CG-MG steps per refinement level,
+# L1..L5 for Bratu and the minimal surface, L1..L4 for the beam
 PAPER_TABLE2 = {'bratu2d-800': [(3, 7), (3, 9), (3, 9), (3, 9), (3, 9)],
-                'minsurf2d-800': [(6, 13), (7, 18), (8, 25), (9, 32), (9, 41)]}
+                'minsurf2d-800': [(6, 13), (7, 18), (8, 25), (9, 32), (9, 41)],
+                'beam3d-160x16x16': [(9, 28), (5, 15), (5, 20), (5, 39)]}
 
 
 def paper_levels():
-    """Table 2's trend on Q1 grids: Bratu and the minimal surface at L1..L5
-    (25 * 2^k elements per axis on k + 1 levels) with the paper's settings,
-    one untimed solve each."""
+    """Table 2's trend on Q1 grids with the paper's settings, one untimed
+    solve each: Bratu and the minimal surface at L1..L5 (25 * 2^k elements
+    per axis on k + 1 levels), the beam at L1..L4 (10 * 2^k x 2^k x 2^k)."""
     import torch
     from paper_2103_13890_amd import api
     from paper_2103_13890_amd import workloads as W
     out = {}
-    for name in ('bratu2d-800', 'minsurf2d-800'):
+    for name in ('bratu2d-800', 'minsurf2d-800', 'beam3d-160x16x16'):
         rows = []
-        for k in range(1, 6):
-            w = W.scaled(name, (25 << k, 25 << k), nlevels=k + 1)
+        for k in range(1, len(PAPER_TABLE2[name]) + 1):
+            n = (10 << k, 1 << k, 1 << k) if name.startswith('beam') else (25 << k, 25 << k)
+            w = W.scaled(name, n, nlevels=k + 1)
             ctx = api.Context(build_problem(w), api.default_options(**w['options']))
             u = torch.from_numpy(W.dirichlet_state(w)).to('cuda')
             rep = api.jfnk_solve(ctx, u, None, torch.zeros_like(u))
@@ -297,7 +299,7 @@ def paper_levels():
                          'paper_newton': p_in, 'paper_cg_mg': p_cg})
             del ctx
         out[name] = rows
-        log(f'{name} L1..L5: Newton {[r["newton"] for r in rows]}, CG-MG {[r["cg_mg"] for r in rows]}, '
+        log(f'{name} by level: Newton {[r["newton"] for r in rows]}, CG-MG {[r["cg_mg"] for r in rows]}, '
             f'GE {[round(r["ge_effective"], 1) for r in rows]}')
     return out
 
