@@ -211,6 +211,10 @@ __device__ __forceinline__ void elem_plap_gauss_fd(const T *x, const T *v, T eps
         } else if (ph.a0 == 2.0) {
             kw[q] = T(1);
             dk[q] = T(0);
+        } else if (ph.a0 == 1.0) {   // k = b^(-1/2): (k_w - k_x)/eps = -dsq / (s_x s_w (s_x + s_w))
+            const T sx = hw_sqrt(bx), sw = hw_sqrt(bw);
+            kw[q] = hw_div(T(1), sw);
+            dk[q] = -hw_div(dsq, sx * sw * (sx + sw));
         } else {
             const T al = T(0.5 * (ph.a0 - 2.0));
             const T kx = (T)pow(bx, al);
@@ -358,7 +362,8 @@ __device__ __forceinline__ T elem_scalar_energy(const T *w, const Phys &ph, T h)
 // element vector, evaluated without subtracting two nearly equal element
 // vectors: with w = x + eps v,
 //   K w = K x + eps K v,   s_w - s_x = eps (2 x^T K v + eps v^T K v) / h^2,
-//   k_w - k_x from that difference (a quotient for p = 3, expm1/log1p else),
+//   k_w - k_x from that difference (quotients for p = 3 and p = 1,
+//   expm1/log1p else),
 // so  q = k_w K v + ((k_w - k_x) / eps) K x  (scaled by h^(d-2)).  Algebraically
 // the same quotient as Sec. 1 with the same eps; only the rounding differs
 // (no cancellation between the two residual evaluations, which in FP32
@@ -424,6 +429,11 @@ __device__ __forceinline__ void elem_scalar_fd(const T *x, const T *v, const T *
         } else if (ph.a0 == 2.0) {
             kw = T(1);
             dk = T(0);
+        } else if (ph.a0 == 1.0) {   // the minimal surface, k = b^(-1/2):
+            // (k_w - k_x) / eps = -dsq / (s_x s_w (s_x + s_w)), s = sqrt(b)
+            const T sx = hw_sqrt(bx), sw = hw_sqrt(bw);
+            kw = hw_div(T(1), sw);
+            dk = -hw_div(dsq, sx * sw * (sx + sw));
         } else {
             const T al = T(0.5 * (ph.a0 - 2.0));
             const T kx = (T)pow(bx, al);
