@@ -70,7 +70,7 @@ template <class F> __device__ __forceinline__ void qn_sums(QnLds &L, int cnt, F 
 
 // Coefficients of H r from L.tot[2k] = s_k.r, L.tot[2k+1] = y_k.r, by the
 // first wave (lane k owns pair k; the recurrences broadcast each new
-// coefficient and update the open sums of the other lanes):
+// coefficient by a lane read and update the open sums of the other lanes):
 // H r = gamma r + sum_k (cs_k s_k + cy_k y_k).
 __device__ __forceinline__ void qn_coeffs(QnLds &L, int np, double gam) {
     const int l = threadIdx.x;
@@ -78,21 +78,21 @@ __device__ __forceinline__ void qn_coeffs(QnLds &L, int np, double gam) {
     // first loop, k = np-1 .. 0: t_l = s_l.r - sum_{j>l} alpha_j s_l.y_j
     double t = on ? L.tot[2 * l] : 0.0, al = 0.0;
     for (int k = np - 1; k >= 0; --k) {
-        const double ak = L.rho[k] * __shfl(t, k);
+        const double ak = L.rho[k] * read_lane(t, k);
         if (l == k) al = ak;
         if (on && l < k) t -= ak * L.sy[l * QN_MAX + k];
     }
     // y_l.q with q = r - sum_j alpha_j y_j
     double yq = on ? L.tot[2 * l + 1] : 0.0;
     for (int j = 0; j < np; ++j) {
-        const double aj = __shfl(al, j);
+        const double aj = read_lane(al, j);
         if (on) yq -= aj * L.yy[l * QN_MAX + j];
     }
     // second loop, k = 0 .. np-1: u_l = gamma y_l.q + sum_{j<l} (alpha_j - beta_j) s_j.y_l
     double u = gam * yq, be = 0.0;
     for (int k = 0; k < np; ++k) {
-        const double bk = L.rho[k] * __shfl(u, k);
-        const double dk = __shfl(al, k) - bk;
+        const double bk = L.rho[k] * read_lane(u, k);
+        const double dk = read_lane(al, k) - bk;
         if (l == k) be = bk;
         if (on && l > k) u += dk * L.sy[k * QN_MAX + l];
     }
