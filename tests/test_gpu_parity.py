@@ -116,9 +116,12 @@ def test_jv_f64(kind, path, form):
 
 # Row-tiled kernel shapes: x extents that are a multiple of 64 (the last node
 # column has its own loader), two wavefronts with a partial second one,
-# natural faces on the high sides, several y tiles and z chunks.
+# natural faces on the high sides, several y tiles and z chunks (below 128
+# elements in x, chunks go down to one plane: the 64 x 30 x 31 case asks for
+# more tiles than its 32 planes times its y tiles, so each chunk is one plane).
 TILE_CASES = [
     ('plap', (64, 17, 9), W.ALL3),
+    ('plap', (64, 30, 31), [(0, 0), (1, 0), (2, 1)]),
     ('plap', (64, 17, 9), [(0, 0), (1, 0), (2, 0)]),
     ('plap_gauss', (64, 17, 9), W.ALL3),
     ('plap_gauss', (128, 9, 5), [(0, 0), (1, 1), (2, 0)]),
