@@ -737,11 +737,16 @@ template void tr_prolong_add<float>(const Exec &, const Grid &, const Grid &, in
 template void tr_prolong_add<double>(const Exec &, const Grid &, const Grid &, int, const double *, double *, double *);
 
 // ---- loads ---------------------------------------------------------------------------
-// b_i = sum over adjacent elements e, Gauss points q: w_q f(x_q) phi_i(x_q)
+// b_i = sum over adjacent elements e, Gauss points q: w_q f(x_q) phi_i(x_q).
+// Each Gaussian of f factors over the axes, and along an axis the Gauss
+// points of the elements on either side of node i take 4 coordinates, so a
+// source costs 4 one-dimensional exponentials per axis instead of one per
+// (element, Gauss point) pair.  The element and Gauss-point loops are
+// unrolled, so the factor table stays in registers.
+template <int D>
 __global__ void k_load_gauss(Grid g, const double *prm, int count, double *b) {
-    const int D = g.dim;
-    const int NV = 1 << D;
-    const double vol = D == 3 ? g.h * g.h * g.h : g.h * g.h;
+    constexpr int NV = 1 << D;
+    const double w = (D == 3 ? g.h * g.h * g.h : g.h * g.h) / NV;
     GRID_STRIDE(i, g.nn) {
         int x, y, z;
         node_coords(g, i, x, y, z);
@@ -749,35 +754,60 @@ __global__ void k_load_gauss(Grid g, const double *prm, int count, double *b) {
             b[i] = 0.0;
             continue;
         }
-        double acc = 0.0;
+        const int X[3] = {x, y, z};
+        const int NE[3] = {g.nx, g.ny, g.nz};
+        unsigned valid = 0;     // bit e: element e (e = sx + 2 sy + 4 sz steps below) inside the grid
+#pragma unroll
         for (int e = 0; e < NV; ++e) {
-            const int ex = x - (e & 1), ey = y - ((e >> 1) & 1), ez = D == 3 ? z - ((e >> 2) & 1) : 0;
-            if (ex < 0 || ex >= g.nx || ey < 0 || ey >= g.ny || (D == 3 && (ez < 0 || ez >= g.nz))) continue;
-            for (int q = 0; q < NV; ++q) {
-                double xq[3];
-                xq[0] = (ex + ((q & 1) ? GL1 : GL0)) * g.h;
-                xq[1] = (ey + (((q >> 1) & 1) ? GL1 : GL0)) * g.h;
-                xq[2] = (ez + (((q >> 2) & 1) ? GL1 : GL0)) * g.h;
-                double f = 0.0;
-                for (int k = 0; k < count; ++k) {
-                    const double *pk = prm + k * (D + 2);
-                    double r2 = 0.0;
-                    for (int a = 0; a < D; ++a) r2 += (xq[a] - pk[a]) * (xq[a] - pk[a]);
-                    const double wd = pk[D];
-                    f += pk[D + 1] * exp(-r2 / (2.0 * wd * wd));
-                }
-                // phi at corner e (local index of node i) evaluated at q
-                int c = __builtin_popcount((unsigned)(e ^ q));
-                double ph = 1.0;
-                for (int a = 0; a < D; ++a) ph *= (a < D - c) ? GL1 : GL0;
-                acc += vol / NV * f * ph;
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int c = X[a] - ((e >> a) & 1);
+                ok = ok && c >= 0 && c < NE[a];
             }
+            if (ok) valid |= 1u << e;
+        }
+        double acc = 0.0;
+        for (int k = 0; k < count; ++k) {
+            const double *pk = prm + k * (D + 2);
+            const double s2 = 2.0 * pk[D] * pk[D];
+            // E[a][2 s + j]: the factor of axis a at Gauss coordinate j of
+            // the element s steps below the node
+            double E[D][4];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double t = (X[a] - (j >> 1) + ((j & 1) ? GL1 : GL0)) * g.h;
+                    E[a][j] = exp(-(t - pk[a]) * (t - pk[a]) / s2);
+                }
+            }
+            double sk = 0.0;
+#pragma unroll
+            for (int e = 0; e < NV; ++e) {
+                double se = 0.0;
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    double f = 1.0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) f *= E[a][2 * ((e >> a) & 1) + ((q >> a) & 1)];
+                    // phi at corner e (local index of node i) evaluated at q
+                    const int c = __builtin_popcount((unsigned)(e ^ q));
+                    double ph = 1.0;
+#pragma unroll
+                    for (int a = 0; a < D; ++a) ph *= (a < D - c) ? GL1 : GL0;
+                    se += f * ph;
+                }
+                if ((valid >> e) & 1u) sk += se;
+            }
+            acc += w * pk[D + 1] * sk;
         }
         b[i] = acc;
     }
 }
 void load_gaussians(const Exec &ex, const Grid &g, const double *prm, int count, double *b) {
-    k_load_gauss<<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, prm, count, b);
+    if (g.dim == 3) k_load_gauss<3><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, prm, count, b);
+    else k_load_gauss<2><<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, prm, count, b);
 }
 
 // traction t on the x = x_max face: each face cell gives t h^2 / 4 to its corners
