@@ -87,7 +87,8 @@ def pcg(A, b, M, tol, maxit):
     """Preconditioned CG on A x = b from x = 0 to ||r|| <= tol (recursive
     residual), M(r) the preconditioner.  Returns (x, iterations, ||r||, ok);
     ok is False at non-positive curvature p^T A p <= 0 or after maxit steps
-    (x is then the last iterate)."""
+    (x is then the last iterate; at non-positive curvature on the first
+    direction it is that direction, the preconditioned residual M(b))."""
     x = np.zeros_like(b)
     r = b.copy()
     rn = np.sqrt(_dot(r, r))
@@ -100,7 +101,9 @@ def pcg(A, b, M, tol, maxit):
         q = A(p)
         pq = _dot(p, q)
         if pq <= 0.0:
-            return x, it, rn, False
+            # truncated Newton-CG (Nocedal and Wright, Alg. 7.1): a first
+            # direction of non-positive curvature is returned itself
+            return (p.copy() if it == 1 else x), it, rn, False
         alpha = rz / pq
         x = x + alpha * p
         r = r - alpha * q

@@ -185,16 +185,22 @@ def solve(problem, finest, nlevels, u0, b, m=None, mg_opts=None, opts=None, repo
 
 
 def load_steps(problem, finest, nlevels, u0, b_final, nsteps, m=None, mg_opts=None, opts=None):
-    """Apply the load in nsteps equal increments, halving a failed increment."""
+    """Apply the load in nsteps equal increments, halving a failed increment.
+
+    Increment k solves at k / nsteps of the load; the last one at the full
+    load exactly.  A failed increment is retried at half its size, and the
+    halved size is kept for the rest of the path."""
     u = u0.copy()
     t, dt = 0.0, 1.0 / nsteps
     reports = []
     while t < 1.0 - 1e-12:
         step = min(dt, 1.0 - t)
-        un, rep = solve(problem, finest, nlevels, u, (t + step) * b_final, m, mg_opts, opts)
-        reports.append((t + step, rep))
+        # increments k / nsteps of the load; the last one is the full load exactly
+        target = 1.0 if t + step >= 1.0 - 1e-12 else t + step
+        un, rep = solve(problem, finest, nlevels, u, target * b_final, m, mg_opts, opts)
+        reports.append((target, rep))
         if rep.status == 'ok':
-            u, t = un, t + step
+            u, t = un, target
         else:
             dt = 0.5 * step
             if dt < 1e-6:
