@@ -120,8 +120,8 @@ typedef struct {
     int restart, max_cycles;            /* 30, restarts per Newton step */
     int newton_maxit;
     double newton_rtol, newton_atol;    /* stop at ||F|| <= max(atol, rtol ||F_0||) */
-    int ls_maxit;
-    double armijo;
+    int ls_maxit;                       /* line-search trials per Newton step (>= 1) */
+    double armijo;                      /* sufficient-decrease constant, in (0, 1); 1e-4 */
     int vcycle_prec;                    /* jfnk_prec of every multigrid level */
     int eps_mode;                       /* jfnk_eps_mode */
     double fd_root;                     /* > 0: replaces sqrt(machine eps) in the FD step */
@@ -153,7 +153,9 @@ typedef struct {
      * V-cycle per step; JFNK_OUTER_CG the paper's CG-MG: conjugate gradients
      * preconditioned by one V-cycle per step, at most restart * max_cycles
      * steps, stopped at ||r|| <= eta ||F|| or at a direction p with
-     * p.Jp <= 0 (the step so far is kept).  CG assumes a symmetric J: it
+     * p.Jp <= 0 (the step so far is kept; on the first direction that
+     * direction itself, the preconditioned residual, as truncated
+     * Newton-CG does).  CG assumes a symmetric J: it
      * is meant for the variational kinds, not JFNK_INVCOEF.
      * jfnk_adjoint_solve always uses FGMRES. */
     int outer_krylov;
@@ -312,13 +314,26 @@ jfnk_status jfnk_vjp(jfnk_ctx *ctx, int level, int wrt, const double *u, const d
 jfnk_status jfnk_adjoint_solve(jfnk_ctx *ctx, const double *u, const double *coef,
                                const double *rhs, double rtol, double *lam, jfnk_report *rep);
 
+/* Gradient of a loss L(u(m)) with respect to the coefficient field, by the
+ * implicit-function theorem: with F(u(m); m) = 0 and lam solving
+ * J(u)^T lam = dL/du (jfnk_adjoint_solve), dL/dm = -(dF/dm)^T lam
+ * (jfnk_vjp with wrt 1, negated here).  INVCOEF only; u, coef, lam, grad:
+ * FP64 finest-level arrays, grad at every node.  Errors: JFNK_E_INVAL for
+ * another kind or a null pointer. */
+jfnk_status jfnk_coef_gradient(jfnk_ctx *ctx, const double *u, const double *coef, const double *lam,
+                               double *grad);
+
 /* ---- load vectors ---------------------------------------------------------- */
 /* kind 0: b_i = sum_e sum_q w_q f(x_q) phi_i(x_q), 2^d Gauss points, with
  *         f(x) = sum_k a_k exp(-|x - c_k|^2 / (2 w_k^2)); params holds, per
- *         Gaussian, (c_x, c_y[, c_z], w, a); nparams = count * (dim + 2).
+ *         Gaussian, (c_x, c_y[, c_z], w, a); nparams = count * (dim + 2),
+ *         at most the number of finest-level nodes (the parameters are
+ *         staged in a node-sized device scratch array).
  * kind 1: surface traction t = (t_x, t_y, t_z) on the x = x_max face
  *         (NEOHOOKE), 2x2 Gauss per face cell; nparams = 3.
- * b: FP64 finest-level array (zero on Dirichlet nodes). */
+ * b: FP64 finest-level array (zero on Dirichlet nodes).
+ * Errors: JFNK_E_INVAL for a null pointer, an unknown kind, a kind that does
+ * not fit the problem, or a parameter count that is not one of the above. */
 jfnk_status jfnk_assemble_load(jfnk_ctx *ctx, int kind, const double *params, int nparams,
                                double *b);
 

@@ -307,6 +307,16 @@ def jfnk_adjoint_solve(ctx, u, rhs, coef=None, rtol=1e-10, lam=None, raise_on_fa
     return lam, d
 
 
+def jfnk_coef_gradient(ctx, u, coef, lam, out=None):
+    L = ctx.nlevels - 1
+    out = ctx.empty(L, torch.float64, comps=False) if out is None else out
+    ctx.check(ctx.lib.jfnk_coef_gradient(ctx.h, _ptr(u, ctx, L, torch.float64, name='u'),
+                                         _ptr(coef, ctx, L, torch.float64, False, 'coef'),
+                                         _ptr(lam, ctx, L, torch.float64, name='lam'),
+                                         _ptr(out, ctx, L, torch.float64, False, 'out')))
+    return out
+
+
 # ---- loads and timers -----------------------------------------------------------------------
 def jfnk_assemble_load(ctx, kind, params, b=None):
     L = ctx.nlevels - 1
@@ -334,7 +344,8 @@ class JFNKSolve(torch.autograd.Function):
     from 0).  Backward (implicit-function theorem): with J(u)^T lam = dL/du
     (jfnk_adjoint_solve, the multigrid of the converged u as preconditioner),
     dL/dcoef = -(dF/dcoef)^T lam (jfnk_vjp, wrt 1) and dL/db = lam.  coef is
-    the INVCOEF field m (None for the other kinds)."""
+    the INVCOEF field m (None for the other kinds); its gradient comes from
+    jfnk_coef_gradient."""
 
     @staticmethod
     def forward(fctx, coef, b, ctx, u0=None, adjoint_rtol=1e-10):
@@ -352,10 +363,9 @@ class JFNKSolve(torch.autograd.Function):
     def backward(fctx, gu):
         ctx = fctx.jctx
         u, coef = fctx.saved_tensors
-        L = ctx.nlevels - 1
         lam, _ = jfnk_adjoint_solve(ctx, u, gu.contiguous().to(torch.float64), coef=coef, rtol=fctx.rtol)
         g_coef = None
         if fctx.has_coef and fctx.needs_input_grad[0]:
-            g_coef = -jfnk_vjp(ctx, L, 1, u, lam, coef=coef)
+            g_coef = jfnk_coef_gradient(ctx, u, coef, lam)
         g_b = lam if fctx.needs_input_grad[1] else None
         return g_coef, g_b, None, None, None

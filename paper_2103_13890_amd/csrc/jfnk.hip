@@ -157,6 +157,7 @@ std::string validate(const jfnk_problem *p, const jfnk_options *o) {
     if (o->outer_krylov != JFNK_OUTER_FGMRES && o->outer_krylov != JFNK_OUTER_CG)
         return "outer_krylov must be FGMRES or CG";
     if (o->newton_maxit < 0 || o->max_cycles < 1 || o->ls_maxit < 1) return "iteration caps must be positive";
+    if (!(o->armijo > 0.0 && o->armijo < 1.0)) return "need 0 < armijo < 1";
     Grid g0 = level_grid(*p, 0);
     if (g0.nn > coarse_max_nodes()) return "coarsest grid too large for the coarse solver: add levels";
     return "";
@@ -737,6 +738,7 @@ jfnk_status run_fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, d
 // ends the solve unconverged with x as it stands.  Vectors: r and p in the
 // first two basis columns, q = A p in w, z in the first preconditioned
 // column.  One host read per step (p.Ap and ||r||^2 after the update).
+// Non-positive curvature on the first direction returns that direction.
 // ---------------------------------------------------------------------------
 template <typename T>
 jfnk_status pcg(jfnk_ctx *c, OpKind op, const double *rhs, double sign, double rhs_norm, double tol, double *x,
@@ -774,7 +776,13 @@ jfnk_status pcg(jfnk_ctx *c, OpKind op, const double *rhs, double sign, double r
         CHK(read_slots(c, S_COEF, 2, h));
         *iters = it;
         if (!std::isfinite(h[0])) return fail(c, JFNK_E_NONFINITE, "CG: non-finite curvature");
-        if (!(h[0] > 0.0)) return JFNK_E_NOCONV;           // x and r unchanged by this step
+        if (!(h[0] > 0.0)) {
+            // x and r unchanged by this step; a first direction of
+            // non-positive curvature is returned itself (truncated
+            // Newton-CG, Nocedal and Wright Alg. 7.1): p = z = M r
+            if (it == 1) HIPCHK(c, hipMemcpyAsync(x, p, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+            return JFNK_E_NOCONV;
+        }
         const double rn = std::sqrt(h[1]);
         if (!std::isfinite(rn)) return fail(c, JFNK_E_NONFINITE, "CG: non-finite residual");
         *est_out = rn;
@@ -1453,6 +1461,16 @@ jfnk_status jfnk_adjoint_solve(jfnk_ctx *c, const double *u, const double *coef,
     return s;
 }
 
+jfnk_status jfnk_coef_gradient(jfnk_ctx *c, const double *u, const double *coef, const double *lam, double *grad) {
+    if (!c) return fail(nullptr, JFNK_E_INVAL, "null context");
+    if (c->prob.kind != JFNK_INVCOEF) return fail(c, JFNK_E_INVAL, "the coefficient gradient needs INVCOEF");
+    if (!u || !coef || !lam || !grad) return fail(c, JFNK_E_INVAL, "null u, coef, lam or grad");
+    const Grid &g = c->lev[c->L].g;
+    const double *k = coef_kap<double>(c, c->L, coef, c->tmpB);
+    op_vjp(c->ex, g, c->ph, k, u, lam, 1, grad, -1.0);
+    return check_launch(c);
+}
+
 jfnk_status jfnk_assemble_load(jfnk_ctx *c, int kind, const double *params, int nparams, double *b) {
     if (!c) return fail(nullptr, JFNK_E_INVAL, "null context");
     if (!b || !params) return fail(c, JFNK_E_INVAL, "null b or params");
@@ -1462,7 +1480,8 @@ jfnk_status jfnk_assemble_load(jfnk_ctx *c, int kind, const double *params, int 
         const int per = g.dim + 2;
         if (nparams <= 0 || nparams % per) return fail(c, JFNK_E_INVAL, "nparams must be a multiple of dim+2");
         const int count = nparams / per;
-        // parameters go to device scratch (tmpA) first
+        // parameters go to device scratch (tmpA, c->n doubles) first
+        if ((long long)nparams > c->n) return fail(c, JFNK_E_INVAL, "too many load parameters for this grid");
         HIPCHK(c, hipMemcpyAsync(c->tmpA, params, nparams * sizeof(double), hipMemcpyHostToDevice, c->st));
         HIPCHK(c, hipStreamSynchronize(c->st));
         load_gaussians(c->ex, g, c->tmpA, count, b);

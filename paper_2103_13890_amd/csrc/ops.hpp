@@ -109,9 +109,9 @@ void op_power(const Exec &, int mode, const Grid &, const Phys &, const T *kap, 
 
 // energy Psi_h(u) (element sum) -> out[0]   (FP64, variational kinds)
 void op_energy(const Exec &, const Grid &, const Phys &, const double *u, double *out);
-// exact VJP: out = J(u)^T lam (wrt 0) or (dF/dm)^T lam (wrt 1, kap = e^m)
+// exact VJP: out = scale J(u)^T lam (wrt 0) or scale (dF/dm)^T lam (wrt 1, kap = e^m)
 void op_vjp(const Exec &, const Grid &, const Phys &, const double *kap, const double *u, const double *lam,
-            int wrt, double *out);
+            int wrt, double *out, double scale = 1.0);
 
 // ---- vectors (n = nodes, nc components, SoA) ---------------------------------
 template <typename T> void vec_fill(const Exec &, T *x, long long n, T val);

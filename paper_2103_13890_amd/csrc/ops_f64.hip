@@ -57,9 +57,10 @@ void op_energy(const Exec &ex, const Grid &g, const Phys &ph, const double *u, d
 // ---- exact VJP ---------------------------------------------------------------------
 // wrt 0: out_i = sum_e (J_e^T lam_e)_{a(i)} on DoFs (lam taken as 0 on Dirichlet nodes)
 // wrt 1: out_i = e^{m_i} sum_e (1 + ubar_e^2)(lam_e^T K_e u_e) / 2^d at every node
+// (both times scale: -1 gives the coefficient gradient -(dF/dm)^T lam exactly)
 template <int DIM, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_vjp(Grid g, Phys ph, const double *kap, const double *u,
-                                               const double *lam, int wrt, double *out) {
+                                               const double *lam, int wrt, double scale, double *out) {
     constexpr int NV = Cell<DIM>::NV;
     constexpr int NC = (KIND == JFNK_NEOHOOKE) ? 3 : 1;
     const long long stride = (long long)gridDim.x * blockDim.x;
@@ -113,32 +114,32 @@ __global__ __launch_bounds__(BLOCK) void k_vjp(Grid g, Phys ph, const double *ka
         }
         if (wrt == 1) acc[0] *= kap[i];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) out[c * g.nn + i] = acc[c];
+        for (int c = 0; c < NC; ++c) out[c * g.nn + i] = scale * acc[c];
     }
 }
 
 void op_vjp(const Exec &ex, const Grid &g, const Phys &ph, const double *kap, const double *u, const double *lam,
-            int wrt, double *out) {
+            int wrt, double *out, double scale) {
     const int nb = node_blocks(g.nn);
     switch (ph.kind) {
     case JFNK_BRATU:
-        if (g.dim == 2) k_vjp<2, JFNK_BRATU><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
-        else k_vjp<3, JFNK_BRATU><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
+        if (g.dim == 2) k_vjp<2, JFNK_BRATU><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
+        else k_vjp<3, JFNK_BRATU><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
         break;
     case JFNK_PLAP:
-        if (g.dim == 2) k_vjp<2, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
-        else k_vjp<3, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
+        if (g.dim == 2) k_vjp<2, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
+        else k_vjp<3, JFNK_PLAP><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
         break;
     case JFNK_INVCOEF:
-        if (g.dim == 2) k_vjp<2, JFNK_INVCOEF><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
-        else k_vjp<3, JFNK_INVCOEF><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
+        if (g.dim == 2) k_vjp<2, JFNK_INVCOEF><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
+        else k_vjp<3, JFNK_INVCOEF><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
         break;
     case JFNK_NEOHOOKE:
-        k_vjp<3, JFNK_NEOHOOKE><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
+        k_vjp<3, JFNK_NEOHOOKE><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
         break;
     case JFNK_PLAP_GAUSS:
-        if (g.dim == 2) k_vjp<2, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
-        else k_vjp<3, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, out);
+        if (g.dim == 2) k_vjp<2, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
+        else k_vjp<3, JFNK_PLAP_GAUSS><<<nb, BLOCK, 0, ex.st>>>(g, ph, kap, u, lam, wrt, scale, out);
         break;
     }
 }

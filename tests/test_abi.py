@@ -78,6 +78,8 @@ def test_workspace_and_validation(lib):
         ('fd_form', dict(fd_form=3)),
         ('kernel_path', dict(kernel_path=5)),
         ('cheb', dict(cheb_lo=1.5)),
+        ('armijo', dict(armijo=1.0)),
+        ('armijo', dict(armijo=0.0)),
     ]
     for what, over in bad:
         st, _ = _bytes(lib, prob, api.default_options(**over))

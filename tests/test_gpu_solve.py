@@ -18,7 +18,7 @@ from _common import make_ctx, ncomp, oracle_grid, oracle_mg_options, oracle_prob
 from oracle import newton as ON
 from oracle import adjoint as OA
 from oracle import problems as OP
-from paper_2103_13890_amd import api
+from paper_2103_13890_amd import _lib, api
 from paper_2103_13890_amd import workloads as W
 
 
@@ -117,8 +117,10 @@ def test_invcoef_solve_and_gradient():
     rhs = to_np(u) - uo_ref
     rhs[g.dirichlet_mask()] = 0
     lam, arep = api.jfnk_adjoint_solve(ctx, u, to_dev(rhs), to_dev(m), rtol=1e-12)
-    gm = -to_np(api.jfnk_vjp(ctx, w['nlevels'] - 1, 1, u, lam, to_dev(m)))
+    gm = to_np(api.jfnk_coef_gradient(ctx, u, to_dev(m), lam))
     assert rel(gm, grad_ref) < 1e-8
+    # the gradient call is the coefficient VJP negated, bit for bit
+    assert np.array_equal(gm, -to_np(api.jfnk_vjp(ctx, w['nlevels'] - 1, 1, u, lam, to_dev(m))))
 
 
 def test_edge_cases():
@@ -142,6 +144,52 @@ def test_edge_cases():
     u = to_dev(np.zeros(oracle_grid(w).node_shape))
     rep = api.jfnk_solve(ctx, u, None, None)
     assert rep['status'] != 'ok'
+
+
+def _status(rep):
+    return rep['status'] if isinstance(rep['status'], str) else _lib.STATUS.get(rep['status'], rep['status'])
+
+
+def test_failure_injection():
+    """Failures forced from the host return their status codes and leave
+    finite state: a NaN in the start state (non-finite residual), a Newton
+    cap of one step, a sufficient-decrease constant of 0.9999 with one trial
+    (a Newton step on a convex energy decreases it by about half the linear
+    prediction, so the line search fails), and a Neo-Hookean load beyond what the increments can
+    carry (inverted elements, halved increments)."""
+    w = small('plap')
+    g = oracle_grid(w)
+    b = to_dev(0.1 * W.normal_vector(w['n'], w['faces'], 300))
+    ctx = make_ctx(w)
+    u0 = np.zeros(g.node_shape)
+    u0[3, 4, 5] = np.nan
+    rep = api.jfnk_solve(ctx, to_dev(u0), None, b)
+    assert _status(rep) == 'nonfinite', rep
+    assert 'non-finite' in rep['error']
+    ctx = make_ctx(w, newton_maxit=1)
+    u = to_dev(np.zeros(g.node_shape))
+    rep = api.jfnk_solve(ctx, u, None, b)
+    assert _status(rep) == 'noconv' and rep['newton_iters'] == 1, rep
+    assert bool(torch.isfinite(u).all()) and bool(u.abs().max() > 0)
+    ctx = make_ctx(w, armijo=0.9999, ls_maxit=1)
+    u = to_dev(np.zeros(g.node_shape))
+    rep = api.jfnk_solve(ctx, u, None, b)
+    assert _status(rep) == 'noconv' and rep['newton_iters'] == 0, rep
+    assert 'line search' in rep['error'] and not torch.any(u)
+    # a traction 500 times the configured one on a short beam, one increment
+    # allowed three Newton steps: every increment fails and is halved until
+    # the step falls below 1e-6; u keeps the last accepted increment
+    wn = small('neohooke-solve')
+    gn = oracle_grid(wn)
+    ctx = make_ctx(wn, newton_maxit=3)
+    t = 500.0 * W.traction(wn.get('traction_seed', 2))
+    bn = api.jfnk_assemble_load(ctx, 1, t)
+    u = to_dev(np.zeros((3,) + gn.node_shape))
+    rep = api.jfnk_solve_steps(ctx, u, 1, None, bn)
+    assert _status(rep) in ('noconv', 'nonfinite'), rep
+    tg = rep['alpha_hist']
+    assert tg[0] == 1.0 and all(tg[k + 1] < tg[k] or tg[k + 1] > tg[k] for k in range(len(tg) - 1))
+    assert bool(torch.isfinite(u).all())
 
 
 def test_autograd_solve_gradients():
