@@ -3,11 +3,16 @@ Neo-Hookean, E = 10, nu = 0.3, (0, 10) x (0, 1)^2 clamped at x = 0 with the
 rotational data on x = 10, the 10 x 1 x 1 coarse mesh refined, the paper's
 solver settings (CG-MG, V(5, 5), coarse CG-QN with the shift).
 
-* L2 (40 x 4 x 4, 3 levels): solved on both sides to ||F|| <= 1e-10, the
-  GPU reaches the oracle's equilibrium to 1e-6 relative, keeps the boundary
-  data, and its coarse solver meets negative curvature.  The Newton paths
-  are not compared step by step: with negative-curvature exits the coarse
-  correction depends on where CG stops, which rounding decides.
+* L2 (40 x 4 x 4, 3 levels): solved on both sides to ||F|| <= 1e-12 (the
+  oracle lands at 3.5e-14 after 7 Newton steps, the FP64 rounding floor),
+  the GPU reaches the oracle's equilibrium to 1e-8 relative, keeps the
+  boundary data, and its coarse solver meets negative curvature.  The bound
+  behind the bar: at the oracle's equilibrium the DoF Jacobian (2925 x 2925,
+  symmetric to 7e-17) has smallest singular value 3.8e-4 (largest 11.75)
+  and ||u|| = 2.43, so ||J^-1|| (||F_gpu|| + ||F_ora||) / ||u|| is ~1e-10.
+  The Newton paths are not compared step by step: with negative-curvature
+  exits the coarse correction depends on where CG stops, which rounding
+  decides.
 * Table 3's finding on L1 and L2, coarse CG and CG-QN: without the shift
   (shift_max = 0: the coarse solver returns at the first direction of
   non-positive curvature) the CG-MG solves need, in total, more than twice
@@ -52,17 +57,20 @@ def test_beam_l2_reaches_oracle_equilibrium():
     mo = OM.MGOptions(nu_pre=o['nu_pre'], nu_post=o['nu_post'], eps_mode='paper', coarse_atol=o['coarse_atol'],
                       coarse_rtol=o['coarse_rtol'], coarse_qn=o['coarse_qn'], shift_gamma=o['shift_gamma'])
     ref, orep = ON.solve(oracle_problem(w), g, w['nlevels'], u0, np.zeros_like(u0), None, mo,
-                         ON.NewtonOptions(rtol=0.0, atol=1e-10, forcing='paper', outer='cg'))
+                         ON.NewtonOptions(rtol=0.0, atol=1e-12, forcing='paper', outer='cg'))
     assert orep.status == 'ok'
     print('beam L2 GPU solve', flush=True)
-    u, rep = _gpu_solve(w, newton_atol=1e-10)
+    u, rep = _gpu_solve(w, newton_atol=1e-12)
     assert rep['status'] == 'ok', rep
-    assert rep['fnorm'] <= 1e-10
+    assert rep['fnorm'] <= 1e-12
+    print(f'final ||F||: GPU {rep["fnorm"]:.2e}, oracle {orep.fnorm[-1]:.2e}', flush=True)
     m = g.dirichlet_mask()
     assert np.array_equal(u[:, m], u0[:, m])
     assert rep['neg_curv'] > 0
     print('newton', rep['newton_iters'], orep.newton_iters, 'cg', rep['lin_hist'], orep.lin, flush=True)
-    assert rel(u, ref) < 1e-6
+    e = rel(u, ref)
+    print(f'beam L2: relative distance to the oracle equilibrium {e:.2e}', flush=True)
+    assert e < 1e-8
 
 
 def test_shift_stabilises_coarse_solver():

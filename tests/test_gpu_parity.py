@@ -4,9 +4,10 @@ seeded inputs, at ragged sizes that span several blocks.
 Tolerances (relative 2-norms):
 * residual F(u), FP64: 1e-12 (two FP64 summation orders differ by ~1e-16).
 * FD Jacobian action with a test step eps = 1e-2 (1 + ||u||)/||v||: 1e-12;
-  the step itself: 1e-14; at the configured step: 1e-6 -- the quotient
+  the step itself: 1e-14; at the configured step: 1e-7 -- the quotient
   amplifies O(1e-16) differences in A by 1/(relative step) ~ 1e8, so two
-  correct FP64 implementations differ by ~1e-8 there.
+  correct FP64 implementations differ by ~1e-8 there (the measured values
+  are printed).
 * transfers: 1e-14 (a few rounded multiply-adds).
 * multigrid components run with the large test step (fd_root = 1e-2) so that
   FD noise does not mask parity: 1e-10.
@@ -109,7 +110,9 @@ def test_jv_f64(kind, path, form):
     Jv, eps = api.jfnk_jv(ctx, L, to_dev(u), to_dev(v), md, want_eps=True)
     eps_o = OM.eps_numerator(g, u, OM.MGOptions()) / OM.dof_norm(g, v)
     assert abs(eps - eps_o) <= 1e-14 * eps_o
-    assert rel(to_np(Jv), OM.fd_jv(pb, g, u, Au, v, m, eps_o)) < 1e-6
+    dev = rel(to_np(Jv), OM.fd_jv(pb, g, u, Au, v, m, eps_o))
+    print(f'J v at the configured step, {kind} path {path} form {form}: {dev:.2e}', flush=True)
+    assert dev < 1e-7
     # against the exact derivative: FD truncation + rounding only
     assert rel(to_np(Jv), OD.jvp(pb, g, u, v, m)) < 1e-5
 
