@@ -29,8 +29,10 @@ namespace jfnk {
 
 // ---- epilogues ---------------------------------------------------------------
 // NS: number of grid sums; NCOMP: components; NIN: values read per node and
-// component.  load(at, in) reads them (issued ahead of the element work by
-// the tiled kernel), node(at, val, dir, sums, in) consumes val at the node;
+// component; VIN: the index of the input that is the FD direction itself
+// (-1: none).  load(at, in) reads them (issued ahead of the element work by
+// the tiled kernel, which passes SKIPV and takes input VIN from the direction
+// plane it holds in LDS), node(at, val, dir, sums, in) consumes val at the node;
 // at addresses the node (PtrAt or BufAt, access.hpp), the component c being
 // c * nn further on.  operator()(totals) runs in the reduction's finishing
 // kernel.
@@ -40,12 +42,13 @@ template <typename T, int NC> struct EpiResidual {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 1;
+    static constexpr int VIN = -1;
     const T *b;
     T *F;
     T *Aout;
     long long nn;
     double *out;
-    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) in[c] = b ? at.ld(b, c * nn) : T(0);
     }
@@ -68,9 +71,10 @@ template <typename T, int NC> struct EpiJv {
     static constexpr int NS = 0;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 0;
+    static constexpr int VIN = -1;
     T *Jv;
     long long nn;
-    template <class At> __device__ __forceinline__ void load(const At &, T *) const {}
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &, T *) const {}
     template <class At>
     __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *, const T *) const {
 #pragma unroll
@@ -86,15 +90,16 @@ template <typename T, int NC> struct EpiCheb {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 3;
+    static constexpr int VIN = 0;
     const T *d;
     T *r, *s, *dn;
     T c1, c2;
     long long nn;
     double *out;
-    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            in[3 * c] = at.ld(d, c * nn);
+            if (!SKIPV) in[3 * c] = at.ld(d, c * nn);
             in[3 * c + 1] = at.ld((const T *)r, c * nn);
             in[3 * c + 2] = at.ld((const T *)s, c * nn);
         }
@@ -126,14 +131,16 @@ template <typename T, int NC> struct EpiChebFirst {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 1;
+    static constexpr int VIN = 0;
     const T *b;
     T *r, *s, *dn;
     T inv_theta, c1, c2;
     long long nn;
     double *out;
-    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) in[c] = at.ld(b, c * nn);
+        for (int c = 0; c < NC; ++c)
+            if (!SKIPV) in[c] = at.ld(b, c * nn);
     }
     template <class At>
     __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *sm, const T *in) const {
@@ -160,15 +167,16 @@ template <typename T, int NC> struct EpiChebLast {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 3;
+    static constexpr int VIN = 0;
     const T *d, *r, *s;
     T *sout;
     T c1, c2;
     long long nn;
     double *out;
-    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            in[3 * c] = at.ld(d, c * nn);
+            if (!SKIPV) in[3 * c] = at.ld(d, c * nn);
             in[3 * c + 1] = at.ld(r, c * nn);
             in[3 * c + 2] = at.ld(s, c * nn);
         }
@@ -194,10 +202,11 @@ template <typename T, int NC> struct EpiResidJv {
     static constexpr int NS = 0;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 1;
+    static constexpr int VIN = -1;
     const T *b;
     T *t;
     long long nn;
-    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) in[c] = at.ld(b, c * nn);
     }
@@ -215,12 +224,13 @@ template <typename T, int NC> struct EpiChebInit {
     static constexpr int NS = 1;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 1;
+    static constexpr int VIN = -1;
     const T *b;
     T *r, *d;
     T inv_theta;
     long long nn;
     double *out;
-    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
         for (int c = 0; c < NC; ++c) in[c] = at.ld(b, c * nn);
     }
@@ -250,15 +260,17 @@ template <typename T, int NC> struct EpiPower {
     static constexpr int NS = 2;
     static constexpr int NCOMP = NC;
     static constexpr int NIN = 1;
+    static constexpr int VIN = 0;
     const T *v;
     T *q;
     long long nn;
     double *out;
     double sc = 0.0;     // 1/||v||, set on the device from the step's norm
     __device__ __forceinline__ void prepare(double n2) { sc = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0; }
-    template <class At> __device__ __forceinline__ void load(const At &at, T *in) const {
+    template <bool SKIPV = false, class At> __device__ __forceinline__ void load(const At &at, T *in) const {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) in[c] = at.ld(v, c * nn);
+        for (int c = 0; c < NC; ++c)
+            if (!SKIPV) in[c] = at.ld(v, c * nn);
     }
     template <class At>
     __device__ __forceinline__ void node(const At &at, const T *val, bool dir, double *sm, const T *in) const {

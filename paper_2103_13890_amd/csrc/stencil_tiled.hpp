@@ -47,6 +47,7 @@ struct TileArgs {
     int nty, ntz;      // tiles along y and z
     int pitch;         // LDS row pitch in entries (>= NX)
     int srows;         // rows per LDS plane slot (node rows + 2)
+    int nt;            // epilogue rows read and written with the non-temporal hint
 };
 
 __device__ __forceinline__ int xcd_tile(int id, int nb) {
@@ -295,24 +296,31 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     // column is finished by thread k.
     constexpr int NIN = Epi::NIN > 0 ? Epi::NIN : 1;
     constexpr bool PLAIN = MODE == M_FD_PLAIN;
+    constexpr bool VLDS = FD && Epi::VIN >= 0 && Epi::NCOMP == 1;
     for (int z = z0 - 1; z < z1; ++z) {
         refresh();
         T pin[R][NIN], pax[R], qin[NIN], qax = T(0);
         if (z >= z0) {
             if (z + 2 <= z1) fetch(z + 2);
-            // clamped row and column: always a valid node, unused where out of the tile
+            // clamped row and column: always a valid node, unused where out of the tile.
+            // An input that is the direction itself is read from its LDS plane
+            // (slot z & 1 holds plane z until store(z + 2)), masked like the
+            // element corners: equal to the array on every free node, and the
+            // epilogues use it on free nodes only.
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int kc = k < urows ? k : urows - 1;
-                const BufAt at{(unsigned)((z * uNY + uy0 + kc) * uNX), (unsigned)tc};
-                epi.load(at, pin[k]);
+                const BufAt at{(unsigned)((z * uNY + uy0 + kc) * uNX), (unsigned)tc, ta.nt != 0};
+                epi.template load<VLDS>(at, pin[k]);
                 pax[k] = PLAIN ? at.ld(Ax, 0) : T(0);
+                if constexpr (VLDS) pin[k][Epi::VIN] = (T)sv[(z & 1) * plane + (kc + 1) * P + t];
             }
             if (extra) {
                 const int kc = t < urows ? t : urows - 1;
                 const PtrAt at{(long long)((z * uNY + uy0 + kc) * uNX + unx)};
-                epi.load(at, qin);
+                epi.template load<VLDS>(at, qin);
                 if constexpr (PLAIN) qax = at.ld(Ax, 0);
+                if constexpr (VLDS) qin[Epi::VIN] = (T)sv[(z & 1) * plane + (kc + 1) * P + unx];
             }
         }
         layer(z);
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                 if (k >= urows) break;
                 const int gy = uy0 + k;
                 if (own_col) {
-                    const BufAt at{(unsigned)((z * uNY + gy) * uNX), (unsigned)t};
+                    const BufAt at{(unsigned)((z * uNY + gy) * uNX), (unsigned)t, ta.nt != 0};
                     const bool dir = zd || ((uodir >> k) & 1u) || xdir_t;
                     T val[1] = {T(0)};
                     if (!dir && !zero_fd) {
