@@ -18,22 +18,18 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, 0x7fffffff, 0x00020000);
 }
 
-// CP: cache policy of the instruction; CP_NT marks data used once (the
-// non-temporal hint of gfx940-class chips), so that streams which cannot stay
-// in the caches do not displace the lines that can
-constexpr int CP_NT = 2;
-template <typename T, int CP = 0> __device__ __forceinline__ T buf_ld(const T *p, unsigned voff, unsigned soff) {
+template <typename T> __device__ __forceinline__ T buf_ld(const T *p, unsigned voff, unsigned soff) {
     if constexpr (sizeof(T) == 4)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(p), (int)voff, (int)soff, CP));
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(p), (int)voff, (int)soff, 0));
     else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(buf_rsrc(p), (int)voff, (int)soff, CP));
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(buf_rsrc(p), (int)voff, (int)soff, 0));
 }
-template <typename T, int CP = 0> __device__ __forceinline__ void buf_st(T *p, unsigned voff, unsigned soff, T v) {
+template <typename T> __device__ __forceinline__ void buf_st(T *p, unsigned voff, unsigned soff, T v) {
     if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), buf_rsrc(p), (int)voff, (int)soff, CP);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), buf_rsrc(p), (int)voff, (int)soff, 0);
     } else {
         using U2 = unsigned __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), buf_rsrc(p), (int)voff, (int)soff, CP);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), buf_rsrc(p), (int)voff, (int)soff, 0);
     }
 }
 
@@ -47,24 +43,17 @@ struct PtrAt {
 // row must be the same in every lane: it is read from the first active lane
 // (a plain copy when the compiler already holds it in a scalar register;
 // otherwise the read keeps it from looping over distinct lane values).
-// nt (block-uniform): the row's data is read or written once by the launch,
-// on a level too large for the caches to keep (non-temporal hint).
 struct BufAt {
     unsigned row;   // index of the row's first node (block-uniform)
     unsigned col;   // the lane's column
-    bool nt = false;
     template <typename T> __device__ __forceinline__ unsigned soff(long long c) const {
         return __builtin_amdgcn_readfirstlane((row + (unsigned)c) * (unsigned)sizeof(T));
     }
     template <typename T> __device__ __forceinline__ T ld(const T *p, long long c) const {
-        T v;
-        if (nt) v = buf_ld<T, CP_NT>(p, col * (unsigned)sizeof(T), soff<T>(c));
-        else v = buf_ld<T>(p, col * (unsigned)sizeof(T), soff<T>(c));
-        return v;
+        return buf_ld<T>(p, col * (unsigned)sizeof(T), soff<T>(c));
     }
     template <typename T> __device__ __forceinline__ void st(T *p, long long c, T v) const {
-        if (nt) buf_st<T, CP_NT>(p, col * (unsigned)sizeof(T), soff<T>(c), v);
-        else buf_st<T>(p, col * (unsigned)sizeof(T), soff<T>(c), v);
+        buf_st<T>(p, col * (unsigned)sizeof(T), soff<T>(c), v);
     }
 };
 

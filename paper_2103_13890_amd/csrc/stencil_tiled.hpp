@@ -47,7 +47,6 @@ struct TileArgs {
     int nty, ntz;      // tiles along y and z
     int pitch;         // LDS row pitch in entries (>= NX)
     int srows;         // rows per LDS plane slot (node rows + 2)
-    int nt;            // epilogue rows read and written with the non-temporal hint
 };
 
 __device__ __forceinline__ int xcd_tile(int id, int nb) {
@@ -129,16 +128,17 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     // registers, across the loop.
     auto sc = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
     int uNX = sc(g.NX), uNY = sc(g.NY), uNZ = sc(g.NZ), unx = sc(g.nx), unz = sc(g.nz), udir = sc(g.dir);
-    int uy0 = sc(y0), urows = sc(rows);
+    int uy0 = sc(y0), urows = sc(rows), usrows = sc(ta.srows);
     unsigned ufree = sc(rfree), ueok = sc(eok), uodir = sc(odir);
     // (the barrier's outputs count as divergent to the compiler, hence the
     // lane reads that mark them uniform again; on scalar registers they are
     // plain copies)
     auto refresh = [&]() {
         asm volatile("" : "+s"(uNX), "+s"(uNY), "+s"(uNZ), "+s"(unx), "+s"(unz), "+s"(udir), "+s"(uy0),
-                     "+s"(urows), "+s"(ufree), "+s"(ueok), "+s"(uodir));
+                     "+s"(urows), "+s"(usrows), "+s"(ufree), "+s"(ueok), "+s"(uodir));
         uNX = sc(uNX); uNY = sc(uNY); uNZ = sc(uNZ); unx = sc(unx); unz = sc(unz); udir = sc(udir);
-        uy0 = sc(uy0); urows = sc(urows); ufree = sc(ufree); ueok = sc(ueok); uodir = sc(uodir);
+        uy0 = sc(uy0); urows = sc(urows); usrows = sc(usrows); ufree = sc(ufree); ueok = sc(ueok);
+        uodir = sc(uodir);
     };
     auto zdir_u = [&](int gz) { return ((udir & JFNK_FACE_ZLO) && gz == 0) || ((udir & JFNK_FACE_ZHI) && gz == unz); };
     auto ydir_u = [&](int gy) { return ((udir & JFNK_FACE_YLO) && gy == 0) || ((udir & JFNK_FACE_YHI) && gy == uNY - 1); };
@@ -189,14 +189,14 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         if (own_col) {
 #pragma unroll
             for (int r = 0; r < R + 2; ++r) {
-                if (r < urows + 2) {
+                if (r < usrows) {
                     sx[sl * plane + r * P + t] = px[r];
                     if constexpr (FD) sv[sl * plane + r * P + t] = pv[r];
                     if constexpr (INV) sk[sl * plane + r * P + t] = pk[r];
                 }
             }
         }
-        if (extra && t < urows + 2) {
+        if (extra && t < usrows) {
             sx[sl * plane + t * P + unx] = qx;
             if constexpr (FD) sv[sl * plane + t * P + unx] = qv;
             if constexpr (INV) sk[sl * plane + t * P + unx] = qk;
@@ -222,16 +222,18 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
         for (int c = 0; c < 4; ++c) { cx[c] = T(0); ck[c] = T(0); cv[c] = TV(0); }
         auto row = [&](int r, T(&ox)[4], TV(&ov)[4], T(&ok)[4]) {
-            const int o = r * P;
+            const int o = (r < usrows ? r : usrows - 1) * P;
             ox[0] = sx[lo + o]; ox[1] = sx[lo + o + 1]; ox[2] = sx[hi + o]; ox[3] = sx[hi + o + 1];
             if constexpr (FD) { ov[0] = sv[lo + o]; ov[1] = sv[lo + o + 1]; ov[2] = sv[hi + o]; ov[3] = sv[hi + o + 1]; }
             if constexpr (INV) { ok[0] = sk[lo + o]; ok[1] = sk[lo + o + 1]; ok[2] = sk[hi + o]; ok[3] = sk[hi + o + 1]; }
         };
         if (lz) row(0, cx, cv, ck);
         T pS0 = T(0), pS1 = T(0), pN0 = T(0), pN1 = T(0);
+        // every element row of the walk is evaluated (rows past the tile
+        // produce values no epilogue stores; past the grid they are
+        // switched off): straight-line code without early exits
 #pragma unroll
         for (int re = 0; re <= R; ++re) {
-            if (re > urows) break;
             T r8[1][8];
             if (lz) {
                 T ux[4], uk[4];
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int kc = k < urows ? k : urows - 1;
-                const BufAt at{(unsigned)((z * uNY + uy0 + kc) * uNX), (unsigned)tc, ta.nt != 0};
+                const BufAt at{(unsigned)((z * uNY + uy0 + kc) * uNX), (unsigned)tc};
                 epi.template load<VLDS>(at, pin[k]);
                 pax[k] = PLAIN ? at.ld(Ax, 0) : T(0);
                 if constexpr (VLDS) pin[k][Epi::VIN] = (T)sv[(z & 1) * plane + (kc + 1) * P + t];
@@ -330,10 +332,9 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
             const bool zd = zdir_u(z);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                if (k >= urows) break;
                 const int gy = uy0 + k;
-                if (own_col) {
-                    const BufAt at{(unsigned)((z * uNY + gy) * uNX), (unsigned)t, ta.nt != 0};
+                if (own_col && k < urows) {
+                    const BufAt at{(unsigned)((z * uNY + gy) * uNX), (unsigned)t};
                     const bool dir = zd || ((uodir >> k) & 1u) || xdir_t;
                     T val[1] = {T(0)};
                     if (!dir && !zero_fd) {
