@@ -219,6 +219,24 @@ jfnk_status jfnk_level_info(const jfnk_ctx *ctx, int level, int n[3],
 jfnk_status jfnk_residual(jfnk_ctx *ctx, int level, int prec, const void *u,
                           const void *coef, const void *b, void *F);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the FP64 residual
+ * F = A_l(u) - b of jfnk_residual without a context.  prob describes the
+ * grid and the residual as for jfnk_workspace_bytes (INVCOEF excepted: its
+ * e^m needs a node-sized array); level in [0, nlevels); u, b (nullable), F:
+ * FP64 device arrays of that level's node layout; fnorm2 (device, nullable)
+ * receives ||F||^2; stream: a hipStream_t (NULL: the default stream).  The
+ * same kernels as jfnk_residual, with their per-block partial sums in a
+ * 128 KB static device array instead of a workspace: no hipMalloc, hipFree
+ * or other allocation is made.  Each GPU has one such array, shared by every
+ * call on it, so calls that overlap on one GPU race (one stream, or ordered
+ * streams, per GPU).  Asynchronous.  Errors (jfnk_last_error(NULL)):
+ * JFNK_E_INVAL for an invalid problem, level or pointer, INVCOEF, or a grid
+ * whose launch needs more partial sums than the array holds (very tall
+ * grids: use jfnk_residual); JFNK_E_DEVICE for a HIP error. */
+jfnk_status jfnk_residual_static(const jfnk_problem *prob, int level, const double *u, const double *b,
+                                 double *F, double *fnorm2, void *stream);
+
 /* Discrete energy Psi_h(u) - b.u on level l (FP64, variational kinds).
  * Blocks; the value goes to *psi (host). */
 jfnk_status jfnk_energy(jfnk_ctx *ctx, int level, const double *u, const double *b,

@@ -69,7 +69,8 @@ class Report(ctypes.Structure):
 
 EXPORTS = [
     'jfnk_default_options', 'jfnk_workspace_bytes', 'jfnk_create', 'jfnk_destroy', 'jfnk_last_error',
-    'jfnk_version', 'jfnk_abi_sizes', 'jfnk_level_info', 'jfnk_residual', 'jfnk_energy', 'jfnk_jv',
+    'jfnk_version', 'jfnk_abi_sizes', 'jfnk_level_info', 'jfnk_residual', 'jfnk_residual_static', 'jfnk_energy',
+    'jfnk_jv',
     'mg_project', 'mg_restrict', 'mg_prolong_add', 'mg_setup', 'mg_reset_eigvecs', 'mg_get_level',
     'mg_get_lambda', 'mg_smooth', 'mg_coarse_solve', 'mg_vcycle', 'jfnk_solve', 'jfnk_solve_steps', 'jfnk_vjp',
     'jfnk_adjoint_solve', 'jfnk_coef_gradient', 'jfnk_assemble_load', 'jfnk_timer_enable', 'jfnk_timer_read',
@@ -99,6 +100,7 @@ def load():
         'jfnk_level_info': (c_int, [vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_longlong),
                                     ctypes.POINTER(ctypes.c_longlong)]),
         'jfnk_residual': (c_int, [vp, c_int, c_int, vp, vp, vp, vp]),
+        'jfnk_residual_static': (c_int, [P, c_int, vp, vp, vp, vp, vp]),
         'jfnk_energy': (c_int, [vp, c_int, vp, vp, ctypes.POINTER(c_dbl)]),
         'jfnk_jv': (c_int, [vp, c_int, c_int, vp, vp, vp, vp, c_dbl, vp, ctypes.POINTER(c_dbl)]),
         'mg_project': (c_int, [vp, c_int, c_int, vp, vp]),

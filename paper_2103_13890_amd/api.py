@@ -155,6 +155,35 @@ def jfnk_residual(ctx, level, u, coef=None, b=None, F=None):
     return F
 
 
+def jfnk_residual_static(problem, level, u, b=None, F=None, fnorm2=None):
+    """F = A_l(u) - b without a context (no allocation by the library); the
+    arrays are FP64 tensors on the current GPU with the level's node layout,
+    fnorm2 (optional) a one-element FP64 tensor that receives ||F||^2.  Runs
+    on the current torch stream."""
+    lib = _lib.load()
+    n = [problem.n[k] >> (problem.nlevels - 1 - level) for k in range(problem.dim)]
+    nc = 3 if problem.kind == _lib.NEOHOOKE else 1
+    shape = tuple(k + 1 for k in reversed(n))
+    shape = ((nc,) + shape) if nc > 1 else shape
+    numel = 1
+    for s in shape:
+        numel *= s
+    F = torch.empty(shape, dtype=torch.float64, device=u.device) if F is None else F
+    for name, t, want in (('u', u, numel), ('b', b, numel), ('F', F, numel), ('fnorm2', fnorm2, 1)):
+        if t is None:
+            continue
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != want:
+            raise ValueError(f'{name} must be a contiguous FP64 GPU tensor of {want} entries')
+    stream = torch.cuda.current_stream(u.device).cuda_stream
+    p = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None)
+    st = lib.jfnk_residual_static(ctypes.byref(problem), int(level), p(u), p(b), p(F), p(fnorm2),
+                                  ctypes.c_void_p(stream))
+    if st != _lib.OK:
+        msg = lib.jfnk_last_error(None)
+        raise JfnkError(st, msg.decode() if msg else '')
+    return F
+
+
 def jfnk_energy(ctx, level, u, b=None):
     out = ctypes.c_double()
     ctx.check(ctx.lib.jfnk_energy(ctx.h, level, _ptr(u, ctx, level, torch.float64, name='u'),

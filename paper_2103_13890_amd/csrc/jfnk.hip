@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "ops.hpp"
@@ -78,6 +79,10 @@ struct jfnk_ctx {
     hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
 };
 
+// Scratch of jfnk_residual_static (below): 128 KB of per-block partial sums.
+constexpr long long STATIC_SCRATCH_DOUBLES = 16384;
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -128,8 +133,8 @@ long long level_dofs(const Grid &g, int nc) {
     return std::max(0LL, nx) * std::max(0LL, ny) * std::max(0LL, nz) * nc;
 }
 
-std::string validate(const jfnk_problem *p, const jfnk_options *o) {
-    if (!p || !o) return "null problem or options";
+std::string validate_problem(const jfnk_problem *p) {
+    if (!p) return "null problem";
     if (p->kind < JFNK_BRATU || p->kind > JFNK_PLAP_GAUSS) return "unknown problem kind";
     if (p->dim != 2 && p->dim != 3) return "dim must be 2 or 3";
     if (p->kind == JFNK_NEOHOOKE && p->dim != 3) return "NEOHOOKE needs dim 3";
@@ -145,6 +150,13 @@ std::string validate(const jfnk_problem *p, const jfnk_options *o) {
     if ((p->kind == JFNK_PLAP || p->kind == JFNK_PLAP_GAUSS) && !(p->param[0] >= 1.0)) return "PLAP needs p >= 1";
     if (p->kind == JFNK_NEOHOOKE && !(p->param[0] > 0.0 && p->param[1] > -1.0 && p->param[1] < 0.5))
         return "NEOHOOKE needs E > 0 and -1 < nu < 0.5";
+    return "";
+}
+
+std::string validate(const jfnk_problem *p, const jfnk_options *o) {
+    if (!p || !o) return "null problem or options";
+    const std::string vp = validate_problem(p);
+    if (!vp.empty()) return vp;
     if (o->restart < 1 || o->restart > MAXR - 1) return "restart must be in [1, 31]";
     if (o->coarse_qn < 0 || o->coarse_qn > QN_MAX) return "coarse_qn must be in [0, 32]";
     if (o->nu_pre < 0 || o->nu_post < 0) return "smoothing degrees must be >= 0";
@@ -976,6 +988,34 @@ template <typename T> const T *coef_kap(jfnk_ctx *c, int level, const double *co
     return scratch;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of jfnk_residual_static: the per-block partial sums of ||F||^2 in
+// a file-scope device array, so that the call allocates nothing.  Every GPU
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress gives on that
+// device (kept per device below), never through the array's name.
+// ---------------------------------------------------------------------------
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[STATIC_MAX_DEVICES] = {};
+
+// the scratch address on the current device (looked up once per device)
+jfnk_status static_scratch(double **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(nullptr, JFNK_E_DEVICE, "hipGetDevice failed");
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(nullptr, JFNK_E_INVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, JFNK_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return JFNK_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1135,6 +1175,32 @@ jfnk_status jfnk_residual(jfnk_ctx *c, int level, int prec, const void *u, const
         op_residual<float>(c->ex, g, c->ph, k, (const float *)u, (const float *)b, (float *)F, nullptr, nullptr);
     }
     return check_launch(c);
+}
+
+jfnk_status jfnk_residual_static(const jfnk_problem *p, int level, const double *u, const double *b, double *F,
+                                 double *fnorm2, void *stream) {
+    const std::string v = validate_problem(p);
+    if (!v.empty()) return fail(nullptr, JFNK_E_INVAL, v);
+    if (p->kind == JFNK_INVCOEF) return fail(nullptr, JFNK_E_INVAL, "INVCOEF needs a node-sized e^m array: use jfnk_residual");
+    if (level < 0 || level >= p->nlevels) return fail(nullptr, JFNK_E_INVAL, "level out of range");
+    if (!u || !F) return fail(nullptr, JFNK_E_INVAL, "null u or F");
+    if (misaligned(u, 8) || misaligned(F, 8) || misaligned(b, 8) || misaligned(fnorm2, 8))
+        return fail(nullptr, JFNK_E_INVAL, "misaligned array");
+    double *part = nullptr;
+    const jfnk_status s = static_scratch(&part);
+    if (s != JFNK_OK) return s;
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    ex.red = Red{part};
+    ex.path = 0;
+    ex.red_cap = STATIC_SCRATCH_DOUBLES;
+    op_residual<double>(ex, level_grid(*p, level), make_phys(*p), nullptr, u, b, F, nullptr, fnorm2);
+    if (ex.red_short)
+        return fail(nullptr, JFNK_E_INVAL, "the grid needs more partial sums than the static scratch holds ("
+                    + std::to_string(STATIC_SCRATCH_DOUBLES) + "): use jfnk_residual");
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, JFNK_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return JFNK_OK;
 }
 
 jfnk_status jfnk_energy(jfnk_ctx *c, int level, const double *u, const double *b, double *psi) {

@@ -11,6 +11,16 @@ struct Exec {
     Red red;
     int path;            // 0 auto, 1 node-centric, 2 z-marching tiles
     LazyTable *lazy = nullptr;   // deferred reductions (nullable)
+    // > 0: red holds this many doubles, and a stencil launch that would need
+    // more partial sums is not made (red_short is set instead); 0: unchecked
+    // (the context's workspace sizes red for every launch it makes)
+    long long red_cap = 0;
+    mutable bool red_short = false;
+    bool red_fits(int nb, int ns) const {
+        if (red_cap <= 0 || (long long)nb * (ns > 0 ? ns : 1) <= red_cap) return true;
+        red_short = true;
+        return false;
+    }
     // when set, recorded on st right after the next stencil kernel (before
     // its reduction finish) and cleared: lets a timer bracket that kernel
     mutable hipEvent_t ev_main_end = nullptr;
