@@ -184,29 +184,121 @@ def gauss_residual(w):
     return r
 
 
-def cpu_baseline(w, ge_effective, ndof):
-    """Oracle sample: fine-level F(u) evaluations at full size on the host."""
+def host_cpu():
+    """The host's CPU model and the threads this process may use."""
+    model = 'unknown'
+    try:
+        with open('/proc/cpuinfo') as fh:
+            for line in fh:
+                if line.startswith('model name'):
+                    model = line.split(':', 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
+
+
+def cpu_baseline(w, rep, ndof):
+    """The NumPy oracle's time for the same solve, extrapolated from timed
+    units of the oracle at full size on the host:
+
+    * t_Jv[l]: an FD product level_jv on each level l (the unit that every
+      gradient evaluation, GE, stands for; the fastest of two or three);
+    * one mg_setup with two fixed power steps, its GEs counted by the
+      oracle's own Stats: its time beyond those GEs is the per-setup work
+      outside GEs (projections, FD step numerators);
+    * one V-cycle (Algorithm 1) on those levels, its GEs counted: its time
+      beyond them is the per-cycle vector work (Chebyshev recurrences,
+      transfers, coarse CG);
+    * FGMRES cycles of 3 and 6 iterations with a diagonal operator and the
+      identity preconditioner: the DCGS2 Arnoldi cost c0 + c1 (j + 1) of an
+      iteration with j + 1 basis vectors, the diagonal product subtracted.
+
+    T = sum_l GE_l t_Jv[l] + N_K (V-cycle work outside GEs) + N_Newton
+    (setup work outside GEs) + sum over the solve's FGMRES iterations of
+    c0 + c1 (j + 1), with GE_l, N_K, N_Newton and the iterations per Newton
+    step (restart 30) those of the GPU solve in rep.  Residual evaluations
+    are priced as FD products (slightly more), so T errs toward a slower
+    oracle only by that."""
+    from oracle import krylov as OK
+    from oracle import mg as OM
     from oracle.fe import Grid
-    from oracle.problems import Problem, residual
+    from oracle.problems import Problem
     from paper_2103_13890_amd import workloads as W
+    o = w['options']
     g = Grid(w['n'], w['h'], w['faces'])
     pb = Problem('plap', {'p': w['params'][0], 'delta': w['params'][1]})
+    opts = OM.MGOptions(nu_pre=o['nu_pre'], nu_post=o['nu_post'], power_fixed=True, power_maxit=2,
+                        coarse_rtol=1e-6)
+    grids = OM.make_grids(g, w['nlevels'])
+    L = w['nlevels'] - 1
     u = 0.01 * W.rough_state(w['n'], w['faces'], 7)
-    b = np.zeros_like(u)
+    wall0, cpu0 = time.perf_counter(), time.process_time()
+
+    st_setup = OM.Stats()
     t0 = time.perf_counter()
-    k = 0
-    while True:
-        residual(pb, g, u, b)
-        k += 1
-        if time.perf_counter() - t0 > 10.0 or k >= 3:
-            break
-    per = (time.perf_counter() - t0) / k
-    est = per * ge_effective
-    return {'value': ndof / est, 'unit': 'DoF/s', 'cores': 1, 'kind': 'oracle',
-            'sample': (f'{k} fine-level F(u) evaluations of the NumPy oracle at 256^3 ({per:.2f} s each, '
-                       f'single-threaded), scaled by the {ge_effective:.0f} effective gradient evaluations '
-                       f'(GE, Sec. 3) of the FP64-multigrid GPU solve; Krylov, transfer and coarse-solve '
-                       f'work not included, so this over-estimates the oracle rate')}
+    levels = OM.mg_setup(pb, grids, u, None, opts, None, st_setup)
+    t_setup = time.perf_counter() - t0
+    t_jv = []
+    for l in range(L + 1):
+        v = W.normal_vector(grids[l].n, w['faces'], 300 + l)
+        best = np.inf
+        for _ in range(3 if l < L else 2):          # the fastest of a few: first touches excluded
+            t0 = time.perf_counter()
+            OM.level_jv(pb, levels[l], v)
+            best = min(best, time.perf_counter() - t0)
+        t_jv.append(best)
+    st_v = OM.Stats()
+    bL = W.normal_vector(w['n'], w['faces'], 310)
+    t0 = time.perf_counter()
+    OM.vcycle(pb, levels, L, bL, opts, st_v)
+    t_v = time.perf_counter() - t0
+    d = 1.0 + np.random.default_rng(11).random(bL.shape)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        _ = d * bL
+    t_diag = (time.perf_counter() - t0) / 3
+    t_k = {}
+    for k in (3, 6):
+        t0 = time.perf_counter()
+        OK.fgmres(lambda z: d * z, bL, lambda v: v, 0.0, restart=k, max_cycles=1)
+        t_k[k] = time.perf_counter() - t0 - k * t_diag
+    wall = time.perf_counter() - wall0
+    cpu = time.process_time() - cpu0
+    # t_k = k c0 + c1 k (k + 1) / 2
+    c1 = max(0.0, (t_k[6] - 2.0 * t_k[3]) / 9.0)
+    c0 = max(0.0, (t_k[3] - 6.0 * c1) / 3.0)
+
+    ge = rep['ge_level']
+    ge_v = [st_v.ge.get(l, 0) for l in range(L + 1)]
+    ge_s = [st_setup.ge.get(l, 0) for l in range(L + 1)]
+    v_extra = max(0.0, t_v - sum(ge_v[l] * t_jv[l] for l in range(L + 1)))
+    s_extra = max(0.0, t_setup - sum(ge_s[l] * t_jv[l] for l in range(L + 1)))
+    nk, nn = rep['linear_iters'], rep['newton_iters']
+    t_arn = 0.0
+    for n in rep['lin_hist'][:nn]:
+        for i in range(n):
+            t_arn += c0 + c1 * (i % 30 + 1)
+    t_ge = sum(ge[l] * t_jv[l] for l in range(L + 1))
+    T = t_ge + nk * v_extra + nn * s_extra + t_arn
+    model, avail = host_cpu()
+    return {'value': ndof / T, 'unit': 'DoF/s', 'cores': round(cpu / wall, 2), 'kind': 'oracle',
+            'extrapolated': True, 'seconds_per_solve': T, 'host_cpu': model, 'host_threads_available': avail,
+            'sample_seconds': round(wall, 1),
+            'units_s': {'jv_per_level': [round(t, 4) for t in t_jv], 'mg_setup_2_power_steps': round(t_setup, 3),
+                        'vcycle': round(t_v, 3), 'vcycle_ge_per_level': ge_v, 'arnoldi_c0': round(c0, 4),
+                        'arnoldi_c1_per_basis_vector': round(c1, 4)},
+            'breakdown_s': {'gradient_evaluations': round(t_ge, 1), 'vcycle_vector_work': round(nk * v_extra, 1),
+                            'setup_outside_ge': round(nn * s_extra, 1), 'arnoldi': round(t_arn, 1)},
+            'sample': (f'timed on the host at full size ({"x".join(map(str, w["n"]))}, {wall:.0f} s): one FD '
+                       f'product per level, one mg_setup (2 power steps), one V-cycle and FGMRES(3), FGMRES(6) '
+                       f'Arnoldi cycles of the NumPy oracle (FP64); extrapolated to this solve\'s counts '
+                       f'({nn} Newton steps, {nk} FGMRES iterations, GE per level {[round(x) for x in ge]}); '
+                       f'cores = process CPU time / wall time over the sample')}
 
 
 def sampled_check(ctx, w, u, b, nsamp=4096):
@@ -304,6 +396,44 @@ def paper_levels():
     return out
 
 
+def oracle_reference(workload):
+    """The oracle's stored tight solve for this workload, if there is one."""
+    path = os.path.join(HERE, 'tests', 'golden', f'ref_{workload}.npz')
+    return np.load(path) if os.path.exists(path) else None
+
+
+def compare_to_reference(u, ref):
+    """||u - u_ora|| / ||u_ora|| on the reference's sampled nodes, and the
+    relative difference of the whole-grid 2-norms."""
+    g = u.double().cpu().numpy().reshape(-1)
+    s = g[ref['nodes']]
+    return {'sampled': float(np.linalg.norm(s - ref['u']) / np.linalg.norm(ref['u'])),
+            'norm': float(abs(np.linalg.norm(g) - float(ref['u_norm'])) / float(ref['u_norm']))}
+
+
+def triad_gbps(n=1 << 28, launches=20):
+    """c = a + s b over 2 GiB FP64 arrays (libjfnk's streaming calibration
+    kernel): the HBM rate a dense sweep reaches, beside the 8 TB/s peak."""
+    import torch
+    from paper_2103_13890_amd import api
+    a = torch.rand(n, dtype=torch.float64, device='cuda')
+    b = torch.rand_like(a)
+    c = torch.empty_like(a)
+    api.jfnk_stream_triad(a, b, c)
+    ok = bool(torch.allclose(c[:1 << 20], a[:1 << 20] + 0.5 * b[:1 << 20]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        api.jfnk_stream_triad(a, b, c)
+    e1.record()
+    torch.cuda.synchronize()
+    avg = e0.elapsed_time(e1) / launches
+    gbs = 24.0 * n / (avg * 1e-3) / 1e9
+    del a, b, c
+    return {'gbps': gbs, 'frac_of_peak': gbs / HBM_PEAK_GBS, 'avg_us': avg * 1e3, 'bytes_per_launch': 24 * n,
+            'launches': launches, 'check': ok}
+
+
 def copy_calibration(nbytes=1 << 30, launches=5):
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -330,6 +460,9 @@ def main():
                     help="skip the paper's three experiments solved with its solver settings")
     ap.add_argument('--no-gauss', action='store_true',
                     help='skip the FP64 residual with the coefficient at each Gauss point')
+    ap.add_argument('--no-paper-fd', action='store_true',
+                    help="skip the FP32-MG solve with the paper's black-box FD quotient on the levels")
+    ap.add_argument('--no-triad', action='store_true', help='skip the streaming triad calibration')
     ap.add_argument('--kernel-path', type=int, default=0)
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a 1 GiB device copy (to scale HBM counters) and exit')
@@ -402,7 +535,27 @@ def main():
         del ctxq, uq, bq
         torch.cuda.empty_cache()
         ctx = None
-    u64 = None
+    u64 = rep64 = None
+    if not args.no_paper_fd:
+        # the paper's black-box FD quotient (F(x + eps v) - F(x)) / eps on the
+        # FP32 levels, eps from the FP32 machine epsilon (fd_form 1)
+        del ctx
+        torch.cuda.empty_cache()
+        ctxp = api.Context(prob, api.default_options(**dict(w['options'], vcycle_prec=1, coarse_rtol=1e-3,
+                                                            fd_form=1, kernel_path=args.kernel_path)))
+        bp = make_load(ctxp, w)
+        up, repsp, secp, _ = timed_solves(ctxp, bp, max(1, min(args.steps, 2)), 1, timers=False)
+        rp = repsp[-1]
+        extra['fp32_mg_paper_quotient'] = {
+            'ms_per_step': secp * 1e3, 'value': ndof / secp, 'ok': all(r['status'] == 'ok' for r in repsp),
+            'status': rp['status'], 'newton': rp['newton_iters'], 'krylov': rp['linear_iters'],
+            'ge_effective': rp['ge_effective'], 'final_rel_residual': rp['fnorm'] / rp['fnorm0'],
+            'rel_diff_vs_difference_form_solution': float(torch.linalg.norm(up - u32) / torch.linalg.norm(u32))}
+        log(f'FP32-MG with the black-box quotient: {rp["status"]}, {secp * 1e3:.1f} ms/solve, Newton '
+            f'{rp["newton_iters"]}, FGMRES {rp["linear_iters"]}')
+        del ctxp, up, bp
+        torch.cuda.empty_cache()
+        ctx = None
     if not args.no_fp64:
         del ctx
         torch.cuda.empty_cache()
@@ -413,6 +566,7 @@ def main():
         b64 = make_load(ctx64, w)
         u64, reps64, sec64, _ = timed_solves(ctx64, b64, args.steps, args.warmup, timers=False)
         ok64 = all(r['status'] == 'ok' for r in reps64)
+        rep64 = reps64[-1]
         extra['fp64_mg'] = {'value': ndof / sec64, 'ms_per_step': sec64 * 1e3, 'ok': ok64,
                             'newton': reps64[-1]['newton_iters'], 'krylov': reps64[-1]['linear_iters'],
                             'ge_effective': reps64[-1]['ge_effective'],
@@ -432,6 +586,13 @@ def main():
             'fp32_mg': float(torch.linalg.norm(u32 - ut) / torch.linalg.norm(ut)),
             'fp64_mg': float(torch.linalg.norm(u64 - ut) / torch.linalg.norm(ut)),
             'tight_status': rt['status'], 'tight_rel_residual': rt['fnorm'] / rt['fnorm0']}
+        ref = oracle_reference(args.workload)
+        if ref is not None:
+            extra['rel_err_vs_oracle_solution'] = {
+                'fp32_mg': compare_to_reference(u32, ref), 'fp64_mg': compare_to_reference(u64, ref),
+                'reference': f'tests/golden/ref_{args.workload}.npz: the oracle\'s FP64 solve to 1e-12, '
+                             f'{len(ref["nodes"])} seeded nodes and the whole-grid 2-norm'}
+            log(f'vs the oracle solution: {extra["rel_err_vs_oracle_solution"]}')
         fres = residual_gbps(ctxt, w)
         extra['fine_residual_f64'] = fres
         log(f'fine F(u) FP64: {fres["gbps"]:.0f} GB/s ({fres["avg_us"]:.1f} us)')
@@ -449,11 +610,15 @@ def main():
     if not args.no_paper:
         extra['paper_settings'] = paper_mode_solves(max(1, min(args.steps, 3)))
         extra['paper_table2_levels'] = paper_levels()
+    if not args.no_triad:
+        torch.cuda.empty_cache()
+        extra['hbm_triad_calibration'] = triad_gbps()
+        log(f'streaming triad: {extra["hbm_triad_calibration"]["gbps"]:.0f} GB/s')
     cpu = None
     if not args.no_cpu:
-        ge_ref = extra.get('fp64_mg', {}).get('ge_effective', ge32)
         log('timing the oracle sample on the host')
-        cpu = cpu_baseline(w, ge_ref, ndof)
+        cpu = cpu_baseline(w, rep64 if rep64 is not None else reps32[-1], ndof)
+        log(f'oracle (extrapolated): {cpu["seconds_per_solve"]:.0f} s/solve from a {cpu["sample_seconds"]} s sample')
 
     out = {
         'metric': 'DoF/s to 1e-8 nonlinear residual, FP32-MG vs FP64-MG; fine F(u) HBM GB/s',

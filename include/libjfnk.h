@@ -356,6 +356,15 @@ jfnk_status jfnk_assemble_load(jfnk_ctx *ctx, int kind, const double *params, in
                                double *b);
 
 /* ---- measurement ----------------------------------------------------------- */
+/* The achievable HBM rate, for reading the kernels' roofline fractions:
+ * c = a + s b over n FP64 elements (device arrays, 16-byte aligned, no
+ * aliasing of c with a or b), a dense grid-wide sweep with 16-byte accesses
+ * and the non-temporal hint, 24 bytes per element.  Asynchronous on stream
+ * (NULL: the default stream).  Errors: JFNK_E_INVAL for n < 0, a null or
+ * misaligned array; JFNK_E_DEVICE for a launch error. */
+jfnk_status jfnk_stream_triad(const double *a, const double *b, double *c, long long n, double s,
+                              void *stream);
+
 /* Kernel classes that can be timed with stream events around each launch. */
 typedef enum {
     JFNK_TIMER_CHEB_FINE = 0,   /* interior fused Chebyshev steps on the finest level */

@@ -73,7 +73,8 @@ EXPORTS = [
     'jfnk_jv',
     'mg_project', 'mg_restrict', 'mg_prolong_add', 'mg_setup', 'mg_reset_eigvecs', 'mg_get_level',
     'mg_get_lambda', 'mg_smooth', 'mg_coarse_solve', 'mg_vcycle', 'jfnk_solve', 'jfnk_solve_steps', 'jfnk_vjp',
-    'jfnk_adjoint_solve', 'jfnk_coef_gradient', 'jfnk_assemble_load', 'jfnk_timer_enable', 'jfnk_timer_read',
+    'jfnk_adjoint_solve', 'jfnk_coef_gradient', 'jfnk_assemble_load', 'jfnk_stream_triad', 'jfnk_timer_enable',
+    'jfnk_timer_read',
 ]
 
 _lib = None
@@ -120,6 +121,7 @@ def load():
         'jfnk_adjoint_solve': (c_int, [vp, vp, vp, vp, c_dbl, vp, R]),
         'jfnk_coef_gradient': (c_int, [vp, vp, vp, vp, vp]),
         'jfnk_assemble_load': (c_int, [vp, c_int, ctypes.POINTER(c_dbl), c_int, vp]),
+        'jfnk_stream_triad': (c_int, [vp, vp, vp, ctypes.c_longlong, c_dbl, vp]),
         'jfnk_timer_enable': (c_int, [vp, c_int, c_int]),
         'jfnk_timer_read': (c_int, [vp, c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_dbl)]),
     }

@@ -355,6 +355,22 @@ def jfnk_assemble_load(ctx, kind, params, b=None):
     return b
 
 
+def jfnk_stream_triad(a, b, c, s=0.5):
+    """c = a + s b on FP64 GPU tensors of equal size (the HBM calibration
+    sweep), on the current torch stream."""
+    lib = _lib.load()
+    for name, t in (('a', a), ('b', b), ('c', c)):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != a.numel():
+            raise ValueError(f'{name} must be a contiguous FP64 GPU tensor of {a.numel()} entries')
+    stream = torch.cuda.current_stream(a.device).cuda_stream
+    st = lib.jfnk_stream_triad(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                               ctypes.c_void_p(c.data_ptr()), a.numel(), float(s), ctypes.c_void_p(stream))
+    if st != _lib.OK:
+        msg = lib.jfnk_last_error(None)
+        raise JfnkError(st, msg.decode() if msg else '')
+    return c
+
+
 def jfnk_timer_enable(ctx, which, enable=True):
     ctx.check(ctx.lib.jfnk_timer_enable(ctx.h, int(which), int(bool(enable))))
 

@@ -1560,6 +1560,18 @@ jfnk_status jfnk_assemble_load(jfnk_ctx *c, int kind, const double *params, int 
     return check_launch(c);
 }
 
+jfnk_status jfnk_stream_triad(const double *a, const double *b, double *c, long long n, double s, void *stream) {
+    if (n < 0) return fail(nullptr, JFNK_E_INVAL, "negative n");
+    if (n == 0) return JFNK_OK;
+    if (!a || !b || !c) return fail(nullptr, JFNK_E_INVAL, "null array");
+    if (misaligned(a, 16) || misaligned(b, 16) || misaligned(c, 16))
+        return fail(nullptr, JFNK_E_INVAL, "arrays must be 16-byte aligned");
+    stream_triad((hipStream_t)stream, a, b, c, n, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, JFNK_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return JFNK_OK;
+}
+
 jfnk_status jfnk_timer_enable(jfnk_ctx *c, int which, int enable) {
     if (!c) return fail(nullptr, JFNK_E_INVAL, "null context");
     if (which < 0 || which >= JFNK_TIMER_COUNT) return fail(c, JFNK_E_INVAL, "unknown timer");

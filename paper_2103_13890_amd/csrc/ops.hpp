@@ -222,4 +222,7 @@ int coarse_max_nodes();
 void load_gaussians(const Exec &, const Grid &, const double *prm, int count, double *b);
 void load_traction(const Exec &, const Grid &, const double *t, double *b);
 
+// streaming calibration c = a + s b (FP64, n elements, a, b, c 16-byte aligned)
+void stream_triad(hipStream_t st, const double *a, const double *b, double *c, long long n, double s);
+
 }  // namespace jfnk

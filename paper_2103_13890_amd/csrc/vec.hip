@@ -1,6 +1,7 @@
 // Vector kernels: masked casts and scalings with fused norms, Chebyshev
 // start/finish, FD-step numerators, SplitMix64 start vectors, Gram-Schmidt
 // passes of flexible GMRES, and load-vector assembly.
+#include <algorithm>
 #include <array>
 #include <utility>
 
@@ -827,6 +828,31 @@ __global__ void k_load_traction(Grid g, double tx, double ty, double tz, double 
 }
 void load_traction(const Exec &ex, const Grid &g, const double *t, double *b) {
     k_load_traction<<<vblocks(g.nn), BLOCK, 0, ex.st>>>(g, t[0], t[1], t[2], b);
+}
+
+// ---- streaming calibration: c = a + s b, 16 bytes per lane and array, with
+// the non-temporal hint (every element is touched once); a dense sweep of
+// the whole arrays by the grid, the access pattern HBM serves best
+typedef double d2v __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void k_triad(const d2v *a, const d2v *b, d2v *c, long long n2, double s) {
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += st) {
+        const d2v x = __builtin_nontemporal_load(&a[i]);
+        const d2v y = __builtin_nontemporal_load(&b[i]);
+        __builtin_nontemporal_store(x + s * y, &c[i]);
+    }
+}
+__global__ void k_triad_tail(const double *a, const double *b, double *c, long long n, double s) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && (n & 1)) c[n - 1] = a[n - 1] + s * b[n - 1];
+}
+void stream_triad(hipStream_t st, const double *a, const double *b, double *c, long long n, double s) {
+    int ncu = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long n2 = n / 2;
+    const long long want = (n2 + 255) / 256;
+    const int nb = (int)std::max(1LL, std::min<long long>(4LL * ncu, want));
+    if (n2 > 0) k_triad<<<nb, 256, 0, st>>>((const d2v *)a, (const d2v *)b, (d2v *)c, n2, s);
+    if (n & 1) k_triad_tail<<<1, 64, 0, st>>>(a, b, c, n, s);
 }
 
 }  // namespace jfnk
