@@ -411,27 +411,30 @@ def compare_to_reference(u, ref):
             'norm': float(abs(np.linalg.norm(g) - float(ref['u_norm'])) / float(ref['u_norm']))}
 
 
-def triad_gbps(n=1 << 28, launches=20):
-    """c = a + s b over 2 GiB FP64 arrays (libjfnk's streaming calibration
-    kernel): the HBM rate a dense sweep reaches, beside the 8 TB/s peak."""
+def triad_gbps(n, nsets=4, launches=40):
+    """c = a + s b over FP64 arrays of n entries (the fine level's node
+    count), rotating over nsets buffer sets as the F(u) timing does
+    (libjfnk's streaming calibration kernel): the HBM rate a dense sweep of
+    arrays of this size reaches, beside the 8 TB/s peak."""
     import torch
     from paper_2103_13890_amd import api
-    a = torch.rand(n, dtype=torch.float64, device='cuda')
-    b = torch.rand_like(a)
-    c = torch.empty_like(a)
-    api.jfnk_stream_triad(a, b, c)
-    ok = bool(torch.allclose(c[:1 << 20], a[:1 << 20] + 0.5 * b[:1 << 20]))
+    sets = [(torch.rand(n, dtype=torch.float64, device='cuda'), torch.rand(n, dtype=torch.float64, device='cuda'),
+             torch.empty(n, dtype=torch.float64, device='cuda')) for _ in range(nsets)]
+    for a, b, c in sets:
+        api.jfnk_stream_triad(a, b, c)
+    a, b, c = sets[0]
+    ok = bool(torch.equal(c, a + 0.5 * b))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(launches):
-        api.jfnk_stream_triad(a, b, c)
+    for i in range(launches):
+        api.jfnk_stream_triad(*sets[i % nsets])
     e1.record()
     torch.cuda.synchronize()
     avg = e0.elapsed_time(e1) / launches
     gbs = 24.0 * n / (avg * 1e-3) / 1e9
-    del a, b, c
+    del sets
     return {'gbps': gbs, 'frac_of_peak': gbs / HBM_PEAK_GBS, 'avg_us': avg * 1e3, 'bytes_per_launch': 24 * n,
-            'launches': launches, 'check': ok}
+            'launches': launches, 'buffers': f'{nsets} rotating sets of a, b, c (FP64, {n} entries)', 'check': ok}
 
 
 def copy_calibration(nbytes=1 << 30, launches=5):
@@ -612,7 +615,7 @@ def main():
         extra['paper_table2_levels'] = paper_levels()
     if not args.no_triad:
         torch.cuda.empty_cache()
-        extra['hbm_triad_calibration'] = triad_gbps()
+        extra['hbm_triad_calibration'] = triad_gbps(nn)
         log(f'streaming triad: {extra["hbm_triad_calibration"]["gbps"]:.0f} GB/s')
     cpu = None
     if not args.no_cpu:
