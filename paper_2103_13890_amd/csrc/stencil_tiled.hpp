@@ -132,10 +132,13 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     unsigned ufree = sc(rfree), ueok = sc(eok), uodir = sc(odir);
     // (the barrier's outputs count as divergent to the compiler, hence the
     // lane reads that mark them uniform again; on scalar registers they are
-    // plain copies)
+    // plain copies).  The Gauss-point kinds go without the barrier: with
+    // their element routine the compiler fails to keep its operands in
+    // scalar registers.
     auto refresh = [&]() {
-        asm volatile("" : "+s"(uNX), "+s"(uNY), "+s"(uNZ), "+s"(unx), "+s"(unz), "+s"(udir), "+s"(uy0),
-                     "+s"(urows), "+s"(usrows), "+s"(ufree), "+s"(ueok), "+s"(uodir));
+        if constexpr (KIND != JFNK_PLAP_GAUSS)
+            asm volatile("" : "+s"(uNX), "+s"(uNY), "+s"(uNZ), "+s"(unx), "+s"(unz), "+s"(udir), "+s"(uy0),
+                         "+s"(urows), "+s"(usrows), "+s"(ufree), "+s"(ueok), "+s"(uodir));
         uNX = sc(uNX); uNY = sc(uNY); uNZ = sc(uNZ); unx = sc(unx); unz = sc(unz); udir = sc(udir);
         uy0 = sc(uy0); urows = sc(urows); usrows = sc(usrows); ufree = sc(ufree); ueok = sc(ueok);
         uodir = sc(uodir);
@@ -235,13 +238,15 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
 #pragma unroll
         for (int re = 0; re <= R; ++re) {
             T r8[1][8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a) r8[0][a] = T(0);
             if (lz) {
                 T ux[4], uk[4];
                 TV uv[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { uk[c] = T(0); uv[c] = TV(0); }
                 row(re + 1, ux, uv, uk);
-                // element urows and columns outside the grid are switched off by
+                // element rows and columns outside the grid are switched off by
                 // the factor m (no branch); their corners hold finite copies
                 const T m = ((ueok >> re) & 1u) ? elane : T(0);
                 // corner a = ax + 2 ay + 4 az
@@ -254,9 +259,6 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
                 elem_eval<3, KIND, MODE, T, 1, 8, PF>(xe, ve, kp, e, ph, h, r8, m);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { cx[c] = ux[c]; cv[c] = uv[c]; ck[c] = uk[c]; }
-            } else {
-#pragma unroll
-                for (int a = 0; a < 8; ++a) r8[0][a] = T(0);
             }
             if (re >= 1) {     // node row re - 1 is complete for this layer
                 const int k = re - 1;
@@ -283,26 +285,31 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         }
     }
 
-    // prologue: planes z0-1 and z0 in LDS, plane z0+1 in registers
+    // prologue: planes z0-1 and z0 in LDS; element layer z0-1 builds the
+    // carry while plane z0+1 is fetched
     fetch(z0 - 1);
     store(z0 - 1);
     fetch(z0);
     store(z0);
+    __syncthreads();
+    refresh();
     fetch(z0 + 1);
+    layer(z0 - 1);
+    __syncthreads();
+    store(z0 + 1);
     __syncthreads();
 
-    // iteration z evaluates element layer z (planes z, z+1 in LDS) and, from
-    // z0 on, finishes node plane z; the first one only builds the carry.
-    // The epilogue inputs of plane z (and A(x) for the plain FD quotient)
-    // are read before the element work.  Node (nx, y0 + k) of the last
-    // column is finished by thread k.
+    // iteration z evaluates element layer z (planes z, z+1 in LDS) and
+    // finishes node plane z.  The epilogue inputs of plane z (and A(x) for
+    // the plain FD quotient) are read before the element work.  Node
+    // (nx, y0 + k) of the last column is finished by thread k.
     constexpr int NIN = Epi::NIN > 0 ? Epi::NIN : 1;
     constexpr bool PLAIN = MODE == M_FD_PLAIN;
     constexpr bool VLDS = FD && Epi::VIN >= 0 && Epi::NCOMP == 1;
-    for (int z = z0 - 1; z < z1; ++z) {
+    for (int z = z0; z < z1; ++z) {
         refresh();
         T pin[R][NIN], pax[R], qin[NIN], qax = T(0);
-        if (z >= z0) {
+        {
             if (z + 2 <= z1) fetch(z + 2);
             // clamped row and column: always a valid node, unused where out of the tile.
             // An input that is the direction itself is read from its LDS plane
@@ -328,7 +335,7 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         layer(z);
         __syncthreads();
         if (z + 2 <= z1) store(z + 2);
-        if (z >= z0) {
+        {
             const bool zd = zdir_u(z);
 #pragma unroll
             for (int k = 0; k < R; ++k) {
