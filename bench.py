@@ -301,6 +301,84 @@ def cpu_baseline(w, rep, ndof):
                        f'cores = process CPU time / wall time over the sample')}
 
 
+ORACLE_PARAMS = {'bratu': ('lam',), 'plap': ('p', 'delta'), 'invcoef': (), 'neohooke': ('E', 'nu')}
+
+
+def oracle_table():
+    """The oracle (NumPy FP64, as it stands) timed on the host: F(u), an FD
+    product and one V-cycle on the 128^3 and 256^3 p-Laplacian grids (the
+    fastest of a few calls; the V-cycle once, on levels set up with two
+    fixed power steps), and full solves to ||F|| <= 1e-8 ||F_0|| from u = 0
+    of the 2D Bratu 32^2, the p-Laplacian 128^3 and the inverse-coefficient
+    problem 128^3 (at m) with their configured multigrid (FP64 levels).
+    The 256^3 solve is the extrapolation of the default run's cpu_baseline."""
+    from oracle import mg as OM
+    from oracle import newton as ON
+    from oracle import problems as OP
+    from oracle.fe import Grid
+    from oracle.problems import Problem
+    from paper_2103_13890_amd import workloads as W
+    model, avail = host_cpu()
+    wall0, cpu0 = time.perf_counter(), time.process_time()
+
+    def setup(name):
+        w = W.WORKLOADS[name]
+        pb = Problem(w['kind'], dict(zip(ORACLE_PARAMS[w['kind']], w['params'])))
+        g = Grid(w['n'], w['h'], w['faces'])
+        o = w['options']
+        mo = OM.MGOptions(nu_pre=o.get('nu_pre', 4), nu_post=o.get('nu_post', 4),
+                          power_fixed=bool(o.get('power_fixed', 0)), power_maxit=o.get('power_maxit', 30),
+                          coarse_rtol=1e-6)
+        return w, pb, g, mo
+
+    def best(fn, k):
+        t = np.inf
+        for _ in range(k):
+            t0 = time.perf_counter()
+            fn()
+            t = min(t, time.perf_counter() - t0)
+        return t
+    units = {}
+    for name in ('plap3d-128', 'plap3d-256'):
+        w, pb, g, mo = setup(name)
+        u = 0.01 * W.rough_state(w['n'], w['faces'], 7)
+        b = np.zeros_like(u)
+        reps = 3 if name.endswith('128') else 2
+        t_f = best(lambda: OP.residual(pb, g, u, b), reps)
+        mo2 = OM.MGOptions(nu_pre=mo.nu_pre, nu_post=mo.nu_post, power_fixed=True, power_maxit=2,
+                           coarse_rtol=1e-6)
+        levels = OM.mg_setup(pb, OM.make_grids(g, w['nlevels']), u, None, mo2)
+        v = W.normal_vector(w['n'], w['faces'], 8)
+        t_jv = best(lambda: OM.level_jv(pb, levels[-1], v), reps)
+        t0 = time.perf_counter()
+        OM.vcycle(pb, levels, w['nlevels'] - 1, v, mo2)
+        t_v = time.perf_counter() - t0
+        units[name] = {'residual_s': t_f, 'fd_jv_s': t_jv, 'vcycle_s': t_v}
+        log(f'oracle units {name}: F {t_f:.3f} s, J v {t_jv:.3f} s, V-cycle {t_v:.2f} s')
+        del levels
+    solves = {}
+    for name in ('bratu2d-32', 'plap3d-128', 'invcoef3d-128'):
+        w, pb, g, mo = setup(name)
+        if w['kind'] == 'bratu':
+            b, m = np.zeros(g.node_shape), None
+        else:
+            c, wd, a = W.gaussian_params(w.get('load_seed', 1), 16, len(w['n']))
+            b = OP.load_from_function(g, OP.gaussian_source(c, wd, a))
+            m = W.matern_field(w['n'], w['h'], w.get('m_seed', 3)) if w['kind'] == 'invcoef' else None
+        t0 = time.perf_counter()
+        _, rep = ON.solve(pb, g, w['nlevels'], np.zeros(g.node_shape), b, m, mo, ON.NewtonOptions(rtol=1e-8))
+        sec = time.perf_counter() - t0
+        ndof = int(np.sum(g.dof_mask()))
+        solves[name] = {'seconds': sec, 'dof_per_s': ndof / sec, 'dofs': ndof, 'status': rep.status,
+                        'newton': rep.newton_iters, 'krylov': rep.linear_iters}
+        log(f'oracle solve {name}: {rep.status}, {sec:.1f} s, {rep.newton_iters} Newton, '
+            f'{rep.linear_iters} Krylov')
+    wall = time.perf_counter() - wall0
+    return {'kind': 'oracle', 'host_cpu': model, 'host_threads_available': avail,
+            'cores': round((time.process_time() - cpu0) / wall, 2), 'units': units, 'solves_to_1e-8': solves,
+            'seconds': round(wall, 1)}
+
+
 def sampled_check(ctx, w, u, b, nsamp=4096):
     """The oracle's residual at sampled nodes of the FP32-MG solution: how far
     the GPU's F(u) is from the oracle's there, and how small the oracle's
@@ -467,6 +545,9 @@ def main():
                     help="skip the FP32-MG solve with the paper's black-box FD quotient on the levels")
     ap.add_argument('--no-triad', action='store_true', help='skip the streaming triad calibration')
     ap.add_argument('--kernel-path', type=int, default=0)
+    ap.add_argument('--oracle-table', action='store_true',
+                    help='only time the oracle on the host (units at 128^3 and 256^3, full solves of the '
+                         '2D Bratu, p-Laplacian 128^3 and inverse-coefficient configurations) and exit')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a 1 GiB device copy (to scale HBM counters) and exit')
     args = ap.parse_args()
@@ -475,6 +556,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.oracle_table:
+        print(json.dumps(oracle_table()), flush=True)
         return
     import torch
     from paper_2103_13890_amd import api
