@@ -50,7 +50,10 @@ def build(verbose=False):
         if verbose and warn:
             print(warn, file=sys.stderr)
     tmp = OUT + '.tmp'
-    cmd = [_hipcc(), f'--offload-arch={ARCH}', '-shared', '-fPIC', '-o', tmp] + [o for o, _ in results]
+    # the marker ranges of the host control (roctx, read by rocprofv3 --marker-trace)
+    rocm_lib = os.path.join(os.environ.get('ROCM_PATH', '/opt/rocm'), 'lib')
+    cmd = ([_hipcc(), f'--offload-arch={ARCH}', '-shared', '-fPIC', '-o', tmp] + [o for o, _ in results] +
+           [f'-L{rocm_lib}', f'-Wl,-rpath,{rocm_lib}', '-lrocprofiler-sdk-roctx'])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError('link failed:\n' + r.stderr)

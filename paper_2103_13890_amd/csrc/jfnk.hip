@@ -12,11 +12,24 @@
 #include <mutex>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ops.hpp"
 
 using namespace jfnk;
 
 namespace {
+
+// A named range on the profiler's marker trace (rocprofv3 --marker-trace):
+// the solve, each Newton step, the multigrid setup, the outer Krylov solve,
+// each V-cycle, the line search and the adjoint solve.  Host-side only; a
+// push and a pop per range.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 constexpr int NSLOT = 1024;
 constexpr size_t PART_CAP = 4096 * 32;    // partial sums (blocks x sums)
@@ -453,6 +466,7 @@ template <typename T> jfnk_status setup_levels(jfnk_ctx *c, const double *u, con
 }
 
 jfnk_status do_setup(jfnk_ctx *c, const double *u, const double *m) {
+    Range range("mg_setup");
     if (c->vprec == JFNK_F32) return setup_levels<float>(c, u, m);
     return setup_levels<double>(c, u, m);
 }
@@ -585,6 +599,7 @@ void vcycle(jfnk_ctx *c, int l, const T *b, T *s_out, double *s_out_n2, const do
 // precondition: z = MG(a v) with v FP64 on the finest level and
 // a = 1/sqrt(*rs) (rs null: a = 1); ||z||^2 -> S_ZN2
 template <typename T> void precondition(jfnk_ctx *c, const double *v, const double *rs, T *z) {
+    Range range("vcycle");
     Level &L = c->lev[c->L];
     if (std::is_same<T, double>::value && rs == nullptr) {
         vcycle<T>(c, c->L, (const T *)v, z, slot(c, S_ZN2));
@@ -807,6 +822,7 @@ jfnk_status pcg(jfnk_ctx *c, OpKind op, const double *rhs, double sign, double r
 // the Newton step's outer solve with the configured Krylov method
 jfnk_status run_outer(jfnk_ctx *c, const double *rhs, double sign, double rhs_norm, double tol, double *x,
                       int *iters, double *est) {
+    Range range("krylov");
     if (c->opt.outer_krylov == JFNK_OUTER_CG) {
         if (c->vprec == JFNK_F32) return pcg<float>(c, OP_FD, rhs, sign, rhs_norm, tol, x, iters, est);
         return pcg<double>(c, OP_FD, rhs, sign, rhs_norm, tol, x, iters, est);
@@ -909,6 +925,7 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
         if (!std::isfinite(fn)) return fail(c, JFNK_E_NONFINITE, "Newton: non-finite residual norm");
         if (fn <= std::max(o.newton_atol, o.newton_rtol * f0)) return JFNK_OK;
         if (k == o.newton_maxit) break;
+        Range step("newton step");
         CHK(do_setup(c, c->u, c->mf));
         const double eta = o.forcing == JFNK_FORCING_PAPER ? std::min(0.5, fn) : std::min(0.5, fn / f0);
         // outer FD step numerator from the FP64 iterate
@@ -936,6 +953,7 @@ jfnk_status newton(jfnk_ctx *c, jfnk_report *rep) {
         double alpha = 1.0, ap = 0.0, pp = 0.0;
         bool have_prev = false, accepted = false;
         double fnt = 0.0, ph = 0.0;
+        Range ls("line search");
         for (int it = 1; it <= o.ls_maxit; ++it) {
             vec_axpy(c->ex, c->n, c->u, alpha, c->dx, c->ut);
             CHK(eval_residual(c, c->ut, c->Ft, c->Aut, S_FT2, true));
@@ -1390,6 +1408,7 @@ jfnk_status mg_vcycle(jfnk_ctx *c, const double *b, double *s) {
 // accepted iterate when write_back or on success.
 static jfnk_status solve_once(jfnk_ctx *c, double *u, const double *coef, const double *b, double scale,
                               jfnk_report *rep, bool write_back, bool first) {
+    Range range("jfnk_solve");
     report_init(c, rep);
     if (first) qn_reset(c);
     HIPCHK(c, hipMemsetAsync(c->scal + S_COARSE, 0, 8 * sizeof(double), c->st));
@@ -1501,6 +1520,7 @@ jfnk_status jfnk_adjoint_solve(jfnk_ctx *c, const double *u, const double *coef,
     if (c->prob.kind == JFNK_INVCOEF && !coef) return fail(c, JFNK_E_INVAL, "INVCOEF needs coef");
     jfnk_report local;
     if (!rep) rep = &local;
+    Range range("adjoint solve");
     report_init(c, rep);
     qn_reset(c);
     HIPCHK(c, hipMemsetAsync(c->scal + S_COARSE, 0, 8 * sizeof(double), c->st));
