@@ -70,19 +70,25 @@ def test_bratu_config_solution():
 
 
 def test_fp32_vcycle_reaches_same_root():
+    # both sides to ||F|| <= 1e-12 ||F_0||, where the solution bar of 1e-8
+    # is meaningful on this grid; the FP32 levels' kernels themselves are
+    # compared with the oracle step by step in test_gpu_fp32_mg.py
     w = W.scaled('plap3d-128', (64, 64, 64), nlevels=4)
     b = _load(w)
-    ref, _ = _oracle_solve(w, b, rtol=1e-10)
+    ref, _ = _oracle_solve(w, b, rtol=1e-12)
     its = {}
     for prec, rtol_c in ((1, 1e-3), (0, 1e-6)):
-        ctx = make_ctx(w, vcycle_prec=prec, coarse_rtol=rtol_c, newton_rtol=1e-10)
+        ctx = make_ctx(w, vcycle_prec=prec, coarse_rtol=rtol_c, newton_rtol=1e-12)
         u = to_dev(np.zeros_like(ref))
         rep = api.jfnk_solve(ctx, u, None, to_dev(b))
         assert rep['status'] == 'ok', rep
-        assert rel(to_np(u), ref) < 1e-7
+        e = rel(to_np(u), ref)
+        print(f'vcycle_prec {prec}: {rep["newton_iters"]} Newton, {rep["linear_iters"]} Krylov, '
+              f'relative difference to the oracle {e:.2e}', flush=True)
+        assert e < 1e-8
         its[prec] = rep['linear_iters']
     # the FP32 V-cycle is as good a preconditioner as the FP64 one
-    assert its[1] <= 2 * its[0] + 5, its
+    assert its[1] <= its[0] + max(2, its[0] // 4), its
 
 
 def test_fp32_vcycle_gauss_kind():
@@ -90,12 +96,12 @@ def test_fp32_vcycle_gauss_kind():
     # kernels in the V-cycle) reaches the oracle's root as the FP64 solve does
     w = small('plap_gauss')
     b = _load(w)
-    ref, _ = _oracle_solve(w, b, rtol=1e-10)
-    ctx = make_ctx(w, vcycle_prec=1, coarse_rtol=1e-3, newton_rtol=1e-10)
+    ref, _ = _oracle_solve(w, b, rtol=1e-12)
+    ctx = make_ctx(w, vcycle_prec=1, coarse_rtol=1e-3, newton_rtol=1e-12)
     u = to_dev(np.zeros_like(ref))
     rep = api.jfnk_solve(ctx, u, None, to_dev(b))
     assert rep['status'] == 'ok', rep
-    assert rel(to_np(u), ref) < 1e-7
+    assert rel(to_np(u), ref) < 1e-8
 
 
 def test_invcoef_solve_and_gradient():
