@@ -74,6 +74,7 @@ struct jfnk_ctx {
     LazyTable lazy;
     // finest level, FP64
     long long nn = 0, n = 0;
+    long long ldv = 0;   // column stride of the Krylov bases V and Z: n rounded up to 64 entries
     double *u = nullptr, *ut = nullptr, *Au = nullptr, *Aut = nullptr, *F = nullptr, *Ft = nullptr;
     double *dx = nullptr, *w = nullptr, *V = nullptr, *bm = nullptr, *kap64 = nullptr;
     double *tmpA = nullptr, *tmpB = nullptr, *lamv = nullptr, *mf = nullptr;
@@ -250,8 +251,11 @@ void plan(jfnk_ctx *c, Carve &cv) {
     c->tmpB = (double *)cv.take(fb);
     c->kap64 = c->prob.kind == JFNK_INVCOEF ? (double *)cv.take((size_t)gf.nn * sizeof(double)) : nullptr;
     c->mf = c->prob.kind == JFNK_INVCOEF ? (double *)cv.take((size_t)gf.nn * sizeof(double)) : nullptr;
-    c->V = (double *)cv.take(fb * (c->opt.restart + 1));
-    c->Z = cv.take((size_t)c->n * es * c->opt.restart);
+    // basis columns start on 512-byte boundaries (the Gram-Schmidt and
+    // combine kernels then read two adjacent entries per 16-byte access)
+    c->ldv = (c->n + 63) / 64 * 64;
+    c->V = (double *)cv.take((size_t)c->ldv * sizeof(double) * (c->opt.restart + 1));
+    c->Z = cv.take((size_t)c->ldv * es * c->opt.restart);
 }
 
 Phys make_phys(const jfnk_problem &p) {
@@ -698,13 +702,13 @@ jfnk_status fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, doubl
         int k = 0;
         for (int j = 0; j < m; ++j) {
             // z_j = M^-1 (u_j / ||u_j||), w = A z_j
-            T *zj = Z + (size_t)j * n;
-            precondition<T>(c, V + (size_t)j * n, j == 0 ? u0n2 : slot(c, S_W2), zj);
+            T *zj = Z + (size_t)j * c->ldv;
+            precondition<T>(c, V + (size_t)j * c->ldv, j == 0 ? u0n2 : slot(c, S_W2), zj);
             CHK(apply_op<T>(c, op, zj, slot(c, S_ZN2), c->w));
             {
                 TimeScope ts(c, JFNK_TIMER_ARNOLDI, false);
-                dcgs_dots(c->ex, n, V, n, j, c->w, slot(c, S_COEF));
-                dcgs_update(c->ex, n, V, n, j, slot(c, S_COEF), c->w, slot(c, S_W2));
+                dcgs_dots(c->ex, n, V, c->ldv, j, c->w, slot(c, S_COEF));
+                dcgs_update(c->ex, n, V, c->ldv, j, slot(c, S_COEF), c->w, slot(c, S_W2));
             }
             CHK(check_launch(c));
             double hh[2 * MAXR + 4];
@@ -744,7 +748,7 @@ jfnk_status fgmres(jfnk_ctx *c, OpKind op, const double *rhs, double sign, doubl
             for (int j = i + 1; j < k; ++j) acc -= Rij(i, j) * y[j];
             y[i] = acc / Rij(i, i);
         }
-        if (k > 0) arn_combine<T>(c->ex, n, Z, n, k, y.data(), x);
+        if (k > 0) arn_combine<T>(c->ex, n, Z, c->ldv, k, y.data(), x);
         CHK(check_launch(c));
         if (est <= tol) converged = true;
     }
@@ -772,7 +776,7 @@ jfnk_status pcg(jfnk_ctx *c, OpKind op, const double *rhs, double sign, double r
                 int *iters, double *est_out) {
     const Grid &g = c->lev[c->L].g;
     const long long n = c->n;
-    double *r = c->V, *p = c->V + n;
+    double *r = c->V, *p = c->V + c->ldv;
     T *z = (T *)c->Z;
     // slots: p.Ap, ||r||^2 (read together), r.z of this and the previous step, ||p||^2
     double *s_pq = slot(c, S_COEF), *s_rn2 = slot(c, S_COEF + 1), *s_rz[2] = {slot(c, S_COEF + 2),

@@ -22,6 +22,10 @@ __device__ __forceinline__ bool dir_at(const Grid &g, long long i) {
     return is_dirichlet(g, x, y, z);
 }
 
+// two FP64 (or FP32) entries per lane access: one 16-byte (8-byte) load
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
 #define GRID_STRIDE(i, n) \
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
@@ -332,12 +336,15 @@ void vec_axpy(const Exec &ex, long long n, const double *x, double a, const doub
 // reads the basis twice instead of three times.
 // The number of basis vectors J is a template parameter, so the loads of a
 // pass issue back to back (the compiler places one wait in front of each
-// use); up to J = 12 a thread also takes two elements per trip.
+// use); up to J = 12 a thread also takes two elements per trip.  When the
+// columns start on 16-byte boundaries (an even leading dimension) those two
+// elements are adjacent and each column is read with one 16-byte load per
+// lane (PAIR); the last element of an odd length goes to the first thread.
 constexpr int ARN_MAX = 32;
 
 template <int J> struct ArnUnroll { static constexpr int U = J <= 12 ? 2 : 1; };
 
-template <int J>
+template <int J, bool PAIR>
 __global__ __launch_bounds__(BLOCK) void k_dcgs_dots(long long n, const double *V, long long ld, const double *w,
                                                      Red red) {
     constexpr int U = ArnUnroll<J>::U;
@@ -357,23 +364,46 @@ __global__ __launch_bounds__(BLOCK) void k_dcgs_dots(long long n, const double *
     };
     const long long stride = (long long)gridDim.x * BLOCK;
     long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    for (; i + (U - 1) * stride < n; i += U * stride) {
-        double ui[U], wi[U], vk[U][J > 0 ? J : 1];
+    if constexpr (PAIR) {
+        const long long n2 = n >> 1;
+        for (long long q = i; q < n2; q += stride) {
+            const long long e = 2 * q;
+            const d2v uu = *(const d2v *)(u + e), ww = *(const d2v *)(w + e);
+            double v0[J > 0 ? J : 1], v1[J > 0 ? J : 1];
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            ui[q] = u[i + q * stride];
-            wi[q] = w[i + q * stride];
-#pragma unroll
-            for (int k = 0; k < J; ++k) vk[q][k] = V[k * ld + i + q * stride];
+            for (int k = 0; k < J; ++k) {
+                const d2v vv = *(const d2v *)(V + k * ld + e);
+                v0[k] = vv.x;
+                v1[k] = vv.y;
+            }
+            acc(uu.x, ww.x, v0);
+            acc(uu.y, ww.y, v1);
         }
+        if ((n & 1) && i == 0) {
+            double vk[J > 0 ? J : 1];
 #pragma unroll
-        for (int q = 0; q < U; ++q) acc(ui[q], wi[q], vk[q]);
-    }
-    if (U > 1 && i < n) {
-        double vk[J > 0 ? J : 1];
+            for (int k = 0; k < J; ++k) vk[k] = V[k * ld + n - 1];
+            acc(u[n - 1], w[n - 1], vk);
+        }
+    } else {
+        for (; i + (U - 1) * stride < n; i += U * stride) {
+            double ui[U], wi[U], vk[U][J > 0 ? J : 1];
 #pragma unroll
-        for (int k = 0; k < J; ++k) vk[k] = V[k * ld + i];
-        acc(u[i], w[i], vk);
+            for (int q = 0; q < U; ++q) {
+                ui[q] = u[i + q * stride];
+                wi[q] = w[i + q * stride];
+#pragma unroll
+                for (int k = 0; k < J; ++k) vk[q][k] = V[k * ld + i + q * stride];
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) acc(ui[q], wi[q], vk[q]);
+        }
+        if (U > 1 && i < n) {
+            double vk[J > 0 ? J : 1];
+#pragma unroll
+            for (int k = 0; k < J; ++k) vk[k] = V[k * ld + i];
+            acc(u[i], w[i], vk);
+        }
     }
     block_partials<NS>(s, red);
 }
@@ -401,7 +431,7 @@ struct FinDcgs {
     }
 };
 
-template <int J>
+template <int J, bool PAIR>
 __global__ __launch_bounds__(BLOCK) void k_dcgs_update(long long n, double *V, long long ld, const double *coef,
                                                        const double *w, Red red) {
     constexpr int U = ArnUnroll<J>::U;
@@ -414,20 +444,52 @@ __global__ __launch_bounds__(BLOCK) void k_dcgs_update(long long n, double *V, l
     const double ir = cs[2 * J], hj = cs[2 * J + 1];
     double *u = V + J * ld, *un = V + (J + 1) * ld;
     double nrm[1] = {0.0};
-    auto one = [&](long long idx, double ui, double wi, const double *vk) {
+    // the new column entry and the next candidate's, from u, w and the basis
+    auto entry = [&](double ui, double wi, const double *vk, double &vj, double &x) {
 #pragma unroll
         for (int k = 0; k < J; ++k) {
             ui -= sk[k] * vk[k];
             wi -= bk[k] * vk[k];
         }
-        const double vj = ui * ir;
-        u[idx] = vj;
-        const double x = wi - hj * vj;
-        un[idx] = x;
+        vj = ui * ir;
+        x = wi - hj * vj;
         nrm[0] += x * x;
+    };
+    auto one = [&](long long idx, double ui, double wi, const double *vk) {
+        double vj, x;
+        entry(ui, wi, vk, vj, x);
+        u[idx] = vj;
+        un[idx] = x;
     };
     const long long stride = (long long)gridDim.x * BLOCK;
     long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if constexpr (PAIR) {
+        const long long n2 = n >> 1;
+        for (long long q = i; q < n2; q += stride) {
+            const long long e = 2 * q;
+            const d2v uu = *(const d2v *)(u + e), ww = *(const d2v *)(w + e);
+            double v0[J > 0 ? J : 1], v1[J > 0 ? J : 1];
+#pragma unroll
+            for (int k = 0; k < J; ++k) {
+                const d2v vv = *(const d2v *)(V + k * ld + e);
+                v0[k] = vv.x;
+                v1[k] = vv.y;
+            }
+            double vj0, x0, vj1, x1;
+            entry(uu.x, ww.x, v0, vj0, x0);
+            entry(uu.y, ww.y, v1, vj1, x1);
+            *(d2v *)(u + e) = d2v{vj0, vj1};
+            *(d2v *)(un + e) = d2v{x0, x1};
+        }
+        if ((n & 1) && i == 0) {
+            double vk[J > 0 ? J : 1];
+#pragma unroll
+            for (int k = 0; k < J; ++k) vk[k] = V[k * ld + n - 1];
+            one(n - 1, u[n - 1], w[n - 1], vk);
+        }
+        block_partials<1>(nrm, red);
+        return;
+    }
     for (; i + (U - 1) * stride < n; i += U * stride) {
         double ui[U], wi[U], vk[U][J > 0 ? J : 1];
 #pragma unroll
@@ -451,16 +513,31 @@ __global__ __launch_bounds__(BLOCK) void k_dcgs_update(long long n, double *V, l
 
 static inline int arn_blocks(long long n) { return vblocks(n, 2048); }
 
+// the 16-byte form while a thread takes two elements per trip and the
+// columns and w start on 16-byte boundaries
+static inline bool arn_pair(const double *V, long long ld, const double *w) {
+    return (ld % 2) == 0 && ((size_t)V % 16) == 0 && ((size_t)w % 16) == 0;
+}
 template <int J> void dcgs_dots_k(const Exec &ex, long long n, const double *V, long long ld, const double *w,
                                   double *coef) {
     const int nb = arn_blocks(n);
-    k_dcgs_dots<J><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, w, ex.red);
+    bool pair = false;
+    if constexpr (ArnUnroll<J>::U == 2) {
+        pair = arn_pair(V, ld, w);
+        if (pair) k_dcgs_dots<J, true><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, w, ex.red);
+    }
+    if (!pair) k_dcgs_dots<J, false><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, w, ex.red);
     finish<2 * J + 2>(ex.st, ex.red, nb, FinDcgs{coef, J});
 }
 template <int J> void dcgs_update_k(const Exec &ex, long long n, double *V, long long ld, const double *coef,
                                     const double *w, double *nrm2) {
     const int nb = arn_blocks(n);
-    k_dcgs_update<J><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, coef, w, ex.red);
+    bool pair = false;
+    if constexpr (ArnUnroll<J>::U == 2) {
+        pair = arn_pair(V, ld, w);
+        if (pair) k_dcgs_update<J, true><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, coef, w, ex.red);
+    }
+    if (!pair) k_dcgs_update<J, false><<<nb, BLOCK, 0, ex.st>>>(n, V, ld, coef, w, ex.red);
     finish<1>(ex.st, ex.red, nb, FinStore<1>{nrm2});
 }
 
@@ -489,9 +566,36 @@ void dcgs_update(const Exec &ex, long long n, double *V, long long ld, int J, co
 struct CombineArgs {
     double y[ARN_MAX];
 };
-template <typename TZ, int K>
+// PAIR: two adjacent entries per lane (x by 16-byte, Z by 16- or 8-byte
+// accesses) when x and the columns of Z start on such boundaries; the same
+// sum per entry, in the same order
+template <typename TZ, int K, bool PAIR>
 __global__ __launch_bounds__(BLOCK) void k_arn_combine(long long n, const TZ *Z, long long ld, CombineArgs ya,
                                                        double *x) {
+    if constexpr (PAIR) {
+        typedef TZ z2v __attribute__((ext_vector_type(2)));
+        const long long n2 = n >> 1;
+        GRID_STRIDE(q, n2) {
+            const long long e = 2 * q;
+            z2v zj[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) zj[j] = *(const z2v *)(Z + j * ld + e);
+            d2v acc = *(const d2v *)(x + e);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                acc.x += ya.y[j] * (double)zj[j].x;
+                acc.y += ya.y[j] * (double)zj[j].y;
+            }
+            *(d2v *)(x + e) = acc;
+        }
+        if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            double acc = x[n - 1];
+#pragma unroll
+            for (int j = 0; j < K; ++j) acc += ya.y[j] * (double)Z[j * ld + n - 1];
+            x[n - 1] = acc;
+        }
+        return;
+    }
     GRID_STRIDE(i, n) {
         TZ zj[K];
 #pragma unroll
@@ -504,7 +608,9 @@ __global__ __launch_bounds__(BLOCK) void k_arn_combine(long long n, const TZ *Z,
 }
 template <typename TZ, int K>
 void arn_combine_k(const Exec &ex, long long n, const TZ *Z, long long ld, const CombineArgs &a, double *x) {
-    k_arn_combine<TZ, K><<<vblocks(n), BLOCK, 0, ex.st>>>(n, Z, ld, a, x);
+    const bool pair = (ld % 2) == 0 && ((size_t)Z % (2 * sizeof(TZ))) == 0 && ((size_t)x % 16) == 0;
+    if (pair) k_arn_combine<TZ, K, true><<<vblocks(n / 2), BLOCK, 0, ex.st>>>(n, Z, ld, a, x);
+    else k_arn_combine<TZ, K, false><<<vblocks(n), BLOCK, 0, ex.st>>>(n, Z, ld, a, x);
 }
 template <typename TZ> using CombFn = void (*)(const Exec &, long long, const TZ *, long long, const CombineArgs &,
                                                double *);
@@ -833,7 +939,6 @@ void load_traction(const Exec &ex, const Grid &g, const double *t, double *b) {
 // ---- streaming calibration: c = a + s b, 16 bytes per lane and array, with
 // the non-temporal hint (every element is touched once); a dense sweep of
 // the whole arrays by the grid, the access pattern HBM serves best
-typedef double d2v __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(256) void k_triad(const d2v *a, const d2v *b, d2v *c, long long n2, double s) {
     const long long st = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += st) {
