@@ -57,3 +57,35 @@ def test_fullsize_residual_and_jv(data, form):
         assert _maxrel(Jv32.reshape(-1)[nodes].double().cpu().numpy(), data['Jv']) < 1e-4
     del ctx
     torch.cuda.empty_cache()
+
+
+def test_residual_beyond_tiled_limit():
+    """A grid past the tiled kernel's limit of 2^28 nodes per array
+    (512 x 768 x 704 elements: 278 M nodes, 2.2 GB per FP64 array), where F(u)
+    runs on the node kernel with 64-bit node indices; through the entry point
+    that needs no context (the workspace of a context this size is tens of
+    GB).  F at 4096 seeded nodes against the oracle (1e-12), ||F||^2 against
+    the sum of squares of F (1e-12)."""
+    n = (512, 768, 704)
+    w = W.scaled('plap3d-256', n, nlevels=7)       # coarsest 8 x 12 x 11
+    p = api.make_problem(w['kind'], w['n'], w['h'], w['faces'], w['params'], w['nlevels'])
+    shape = (n[2] + 1, n[1] + 1, n[0] + 1)
+    nn = shape[0] * shape[1] * shape[2]
+    assert nn >= 1 << 28
+    print(f'{nn} nodes', flush=True)
+    gen = torch.Generator(device='cuda').manual_seed(600)
+    u = 0.6 * (torch.rand(shape, dtype=torch.float64, device='cuda', generator=gen) - 0.5)
+    b = 0.1 * torch.randn(shape, dtype=torch.float64, device='cuda', generator=gen)
+    n2 = torch.zeros(1, dtype=torch.float64, device='cuda')
+    F = api.jfnk_residual_static(p, w['nlevels'] - 1, u, b, None, n2)
+    nodes = np.random.default_rng(601).choice(nn, NSAMP, replace=False)
+    Fs = F.reshape(-1)[torch.from_numpy(nodes).cuda()].cpu().numpy()
+    s2 = float((F * F).sum())
+    un, bn = u.cpu().numpy(), b.cpu().numpy()
+    del u, b, F
+    torch.cuda.empty_cache()
+    Fo = OP.residual_at(oracle_problem(w), oracle_grid(w), un, bn, nodes)
+    e = _maxrel(Fs, Fo)
+    print(f'278M-node F(u): max relative difference {e:.2e} at {NSAMP} nodes', flush=True)
+    assert e < 1e-12
+    assert abs(float(n2[0]) - s2) <= 1e-12 * s2

@@ -130,6 +130,10 @@ TILE_CASES = [
     ('plap_gauss', (128, 9, 5), [(0, 0), (1, 1), (2, 0)]),
     ('invcoef', (100, 19, 7), [(0, 1), (1, 1), (2, 0)]),
     ('bratu', (33, 9, 13), W.ALL3),
+    # the tiled kernel's widest rows: 512 threads (8 wavefronts) per block,
+    # the last node column (x = 512) finished through the extra-column path
+    ('plap', (512, 10, 10), [(0, 0), (1, 1), (2, 0)]),
+    ('invcoef', (512, 9, 11), W.ALL3),
 ]
 
 
