@@ -24,7 +24,10 @@ arithmetic of the method).  Usage:
     python tests/golden/make_fullsize_refs.py plap3d-128 invcoef3d-128 plap3d-256 neohooke-256x64
 
 Each configuration runs in its own process; the 256^3 solve takes hours on
-one core.
+one core.  Options: --out DIR writes the files there instead; --progress
+prints a line at every finest-level V-cycle and every Newton step (the
+oracle's arithmetic is untouched: the V-cycle and setup functions the
+Newton loop calls are wrapped by a logger).
 """
 import os
 import sys
@@ -45,6 +48,26 @@ from oracle.problems import Problem       # noqa: E402
 from paper_2103_13890_amd import workloads as W   # noqa: E402
 
 PARAMS = {'plap': ('p', 'delta'), 'invcoef': (), 'neohooke': ('E', 'nu')}
+OUT = HERE
+
+
+def _progress():
+    """Log every finest-level V-cycle and every multigrid setup (one per
+    Newton step) that the oracle's Newton loop runs."""
+    vcycle, setup = ON.vcycle, ON.mg_setup
+    count = {'v': 0, 's': 0}
+
+    def vcycle_logged(problem, levels, l, b, opts, stats=None):
+        count['v'] += 1
+        _log(f'V-cycle {count["v"]}')
+        return vcycle(problem, levels, l, b, opts, stats)
+
+    def setup_logged(*a, **k):
+        count['s'] += 1
+        _log(f'setup {count["s"]} (Newton step)')
+        return setup(*a, **k)
+    ON.vcycle = vcycle_logged
+    ON.mg_setup = setup_logged
 NSAMPLE = 8192
 SAMPLE_SEED = 2024
 
@@ -122,11 +145,19 @@ def make(name):
     else:
         raise KeyError(name)
     out.update(f0=rep.fnorm[0], f=rep.fnorm[-1], newton=rep.newton_iters, krylov=rep.linear_iters)
-    path = os.path.join(HERE, f'ref_{name}.npz')
+    path = os.path.join(OUT, f'ref_{name}.npz')
     np.savez_compressed(path, **{k: np.asarray(v) for k, v in out.items()})
     _log(f'wrote {path}')
 
 
 if __name__ == '__main__':
-    for nm in sys.argv[1:]:
+    args = sys.argv[1:]
+    if '--out' in args:
+        i = args.index('--out')
+        OUT = args[i + 1]
+        del args[i:i + 2]
+    if '--progress' in args:
+        args.remove('--progress')
+        _progress()
+    for nm in args:
         make(nm)
