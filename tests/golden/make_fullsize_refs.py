@@ -28,6 +28,12 @@ one core.  Options: --out DIR writes the files there instead; --progress
 prints a line at every finest-level V-cycle and every Newton step (the
 oracle's arithmetic is untouched: the V-cycle and setup functions the
 Newton loop calls are wrapped by a logger).
+
+A long solve can run in pieces: --checkpoint FILE saves the Newton iterate
+(with ||F(0)||) at the start of every Newton step, and --resume FILE starts
+the oracle's Newton solve from that iterate with the same absolute target,
+||F|| <= tol ||F(0)||.  The root is the same whatever the path; only the
+iteration counts stored with it then cover the last piece.
 """
 import os
 import sys
@@ -49,6 +55,8 @@ from paper_2103_13890_amd import workloads as W   # noqa: E402
 
 PARAMS = {'plap': ('p', 'delta'), 'invcoef': (), 'neohooke': ('E', 'nu')}
 OUT = HERE
+CHECKPOINT = None
+RESUME = None
 
 
 def _progress():
@@ -95,7 +103,27 @@ def _solve(pb, g, L, b, m, mo, rtol, tag):
     t = time.time()
     nc = pb.ncomp
     u0 = np.zeros(g.node_shape if nc == 1 else (nc,) + g.node_shape)
-    u, rep = ON.solve(pb, g, L, u0, b, m, mo, ON.NewtonOptions(rtol=rtol, maxit=60), rep)
+    # ||F(0)||, as the Newton solve computes it
+    f0 = float(np.linalg.norm(OP._mask(g, nc, OP.apply_A(pb, g, u0, m) - b)))
+    opts = ON.NewtonOptions(rtol=rtol, maxit=60)
+    if RESUME:
+        ck = np.load(RESUME)
+        u0, f0 = ck['u'], float(ck['f0'])
+        opts = ON.NewtonOptions(rtol=0.0, atol=rtol * f0, maxit=60)
+        _log(f'{tag}: resuming from {RESUME} (||F(0)|| = {f0:.6e})')
+    if CHECKPOINT:
+        setup = ON.mg_setup
+
+        def setup_saving(problem, grids, u, *a, **k):
+            tmp = CHECKPOINT + '.tmp.npz'             # replaced in one step: a kill leaves the last one whole
+            np.savez(tmp, u=u, f0=f0)
+            os.replace(tmp, CHECKPOINT)
+            _log(f'checkpoint written to {CHECKPOINT}')
+            return setup(problem, grids, u, *a, **k)
+        ON.mg_setup = setup_saving
+    u, rep = ON.solve(pb, g, L, u0, b, m, mo, opts, rep)
+    if RESUME:
+        rep.fnorm[0] = f0                             # the target and the stored f0 refer to F(0)
     _log(f'{tag}: {rep.status}, {rep.newton_iters} Newton, {rep.linear_iters} Krylov, '
          f'|F|/|F0| = {rep.fnorm[-1] / rep.fnorm[0]:.3e}, {time.time() - t:.0f} s')
     if rep.status != 'ok':
@@ -159,5 +187,13 @@ if __name__ == '__main__':
     if '--progress' in args:
         args.remove('--progress')
         _progress()
+    for opt in ('--checkpoint', '--resume'):
+        if opt in args:
+            i = args.index(opt)
+            if opt == '--checkpoint':
+                CHECKPOINT = args[i + 1]
+            else:
+                RESUME = args[i + 1]
+            del args[i:i + 2]
     for nm in args:
         make(nm)
