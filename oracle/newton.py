@@ -52,6 +52,9 @@ class NewtonOptions:
     armijo: float = 1e-4
     merit: str = 'auto'              # 'auto': energy if variational; 'residual'
     outer: str = 'fgmres'            # 'fgmres' or 'cg'
+    f0: float = 0.0                  # > 0: ||F_0|| of the solve this one continues
+                                     # (from its saved iterate); the forcing and the
+                                     # stop are relative to it
 
 
 @dataclass
@@ -122,8 +125,8 @@ def solve(problem, finest, nlevels, u0, b, m=None, mg_opts=None, opts=None, repo
     Au = apply_A(problem, g, u, m)
     st.count(L)
     F = _mask(g, nc, Au - b)
-    f0 = _norm(F)
-    rep.fnorm.append(f0)
+    rep.fnorm.append(_norm(F))
+    f0 = opts.f0 if opts.f0 > 0.0 else rep.fnorm[0]
     eigs = None
     qn = {}                                   # coarse L-BFGS pairs, built once per solve
     for k in range(opts.maxit + 1):

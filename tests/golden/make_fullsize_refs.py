@@ -30,10 +30,11 @@ oracle's arithmetic is untouched: the V-cycle and setup functions the
 Newton loop calls are wrapped by a logger).
 
 A long solve can run in pieces: --checkpoint FILE saves the Newton iterate
-(with ||F(0)||) at the start of every Newton step, and --resume FILE starts
-the oracle's Newton solve from that iterate with the same absolute target,
-||F|| <= tol ||F(0)||.  The root is the same whatever the path; only the
-iteration counts stored with it then cover the last piece.
+(with ||F(0)||) at the start of every Newton step, and --resume FILE
+continues the oracle's Newton solve from that iterate with forcing and stop
+relative to the same ||F(0)|| (NewtonOptions.f0).  The root is the same
+whatever the path; only the iteration counts stored with it then cover the
+last piece.
 """
 import os
 import sys
@@ -109,7 +110,7 @@ def _solve(pb, g, L, b, m, mo, rtol, tag):
     if RESUME:
         ck = np.load(RESUME)
         u0, f0 = ck['u'], float(ck['f0'])
-        opts = ON.NewtonOptions(rtol=0.0, atol=rtol * f0, maxit=60)
+        opts = ON.NewtonOptions(rtol=rtol, f0=f0, maxit=60)
         _log(f'{tag}: resuming from {RESUME} (||F(0)|| = {f0:.6e})')
     if CHECKPOINT:
         setup = ON.mg_setup

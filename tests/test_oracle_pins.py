@@ -25,6 +25,9 @@
 * ``pcg`` (the paper's outer CG-MG): non-positive curvature on the first
   direction returns that direction, the preconditioned residual (the
   truncated Newton-CG rule of Nocedal and Wright, Alg. 7.1).
+* ``solve`` continued from a saved iterate with ``NewtonOptions.f0`` keeps
+  the original solve's forcing and stop (the full-size references are
+  computed in pieces this way).
 """
 import numpy as np
 import pytest
@@ -210,6 +213,33 @@ def test_load_steps_single_step_is_a_solve():
     u2, reps = newton.load_steps(pb, g, 2, np.zeros(g.node_shape), b, 1, None, mo, no)
     assert r1.status == 'ok' and len(reps) == 1 and reps[0][0] == 1.0
     assert np.array_equal(u1, u2)
+
+
+def test_solve_continued_from_a_saved_iterate():
+    """A solve stopped after two Newton steps and continued from its iterate
+    with NewtonOptions.f0 = the first solve's ||F_0|| takes the same forcing
+    and stop: it meets ||F|| <= rtol ||F_0|| of the original start and reaches
+    the uninterrupted solve's root; without f0 its forcing starts again at
+    0.5 and its stop is relative to the continued start."""
+    g = Grid((16, 16), 1 / 16, [(a, s) for a in range(2) for s in range(2)])
+    pb = Problem('bratu', {'lam': 5.0})
+    b = np.zeros(g.node_shape)
+    from oracle.mg import MGOptions
+    mo = MGOptions(nu_pre=2, nu_post=2, power_fixed=True, power_maxit=5)
+    u0 = np.zeros(g.node_shape)
+    uf, rf = newton.solve(pb, g, 2, u0, b, None, mo, newton.NewtonOptions(rtol=1e-10))
+    assert rf.status == 'ok' and rf.newton_iters >= 3
+    f0 = rf.fnorm[0]
+    u2, r2 = newton.solve(pb, g, 2, u0, b, None, mo, newton.NewtonOptions(rtol=1e-10, maxit=2))
+    assert r2.status == 'noconv' and r2.newton_iters == 2
+    uc, rc = newton.solve(pb, g, 2, u2, b, None, mo, newton.NewtonOptions(rtol=1e-10, f0=f0))
+    assert rc.status == 'ok'
+    assert rc.fnorm[-1] <= 1e-10 * f0
+    assert rc.eta[0] == min(0.5, rc.fnorm[0] / f0)
+    assert np.linalg.norm(uc - uf) <= 1e-9 * np.linalg.norm(uf)
+    # the same continuation without f0: forcing and stop relative to F(u2)
+    _, rn = newton.solve(pb, g, 2, u2, b, None, mo, newton.NewtonOptions(rtol=1e-10, maxit=1))
+    assert rn.eta[0] == 0.5
 
 
 def _run_ls(phi, phi0, slope, maxit=10, armijo=1e-4, fnorm=None, fnorm0=None):
