@@ -26,15 +26,6 @@ __device__ __forceinline__ bool dir_at(const Grid &g, long long i) {
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 
-// Workgroup ids are dealt round-robin over the 8 XCDs; this maps them so that
-// the blocks of one XCD take a contiguous range of virtual ids (and so of
-// nodes or rows), and the neighbouring data they read stays in that XCD's L2.
-__device__ __forceinline__ int xcd_contiguous(int id, int nb) {
-    const int q = nb / 8, r = nb % 8;
-    const int xcd = id % 8, loc = id / 8;
-    return xcd < r ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
-}
-
 #define GRID_STRIDE(i, n) \
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
@@ -725,12 +716,7 @@ __global__ void k_restrict(Grid gf, Grid gc, int nc, const T *rf, T *rc, Red red
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_restrict3(Grid gf, Grid gc, const T *rf, T *rc, Red red, double *out) {
     double sm[1] = {0.0};
-    // a contiguous range of coarse nodes per block, XCD-contiguous, so the
-    // fine rows shared by neighbouring coarse rows are read from one L2
-    const long long per = (gc.nn + gridDim.x - 1) / gridDim.x;
-    const long long i0 = (long long)xcd_contiguous(blockIdx.x, gridDim.x) * per;
-    const long long i1 = i0 + per < gc.nn ? i0 + per : gc.nn;
-    for (long long i = i0 + threadIdx.x; i < i1; i += BLOCK) {
+    GRID_STRIDE(i, gc.nn) {
         int cx, cy, cz;
         node_coords(gc, i, cx, cy, cz);
         T acc = T(0);
