@@ -34,7 +34,9 @@ A long solve can run in pieces: --checkpoint FILE saves the Newton iterate
 continues the oracle's Newton solve from that iterate with forcing and stop
 relative to the same ||F(0)|| (NewtonOptions.f0).  The root is the same
 whatever the path; only the iteration counts stored with it then cover the
-last piece.
+last piece.  --checkpoint-f32 stores the iterate rounded to FP32 and
+compressed (a 256^3 iterate then fits a 64 MB transfer); the continued solve
+starts from that rounded iterate, which moves its path, not its root.
 """
 import os
 import sys
@@ -57,6 +59,7 @@ from paper_2103_13890_amd import workloads as W   # noqa: E402
 PARAMS = {'plap': ('p', 'delta'), 'invcoef': (), 'neohooke': ('E', 'nu')}
 OUT = HERE
 CHECKPOINT = None
+CHECKPOINT_F32 = False
 RESUME = None
 
 
@@ -109,7 +112,7 @@ def _solve(pb, g, L, b, m, mo, rtol, tag):
     opts = ON.NewtonOptions(rtol=rtol, maxit=60)
     if RESUME:
         ck = np.load(RESUME)
-        u0, f0 = ck['u'], float(ck['f0'])
+        u0, f0 = ck['u'].astype(np.float64), float(ck['f0'])
         opts = ON.NewtonOptions(rtol=rtol, f0=f0, maxit=60)
         _log(f'{tag}: resuming from {RESUME} (||F(0)|| = {f0:.6e})')
     if CHECKPOINT:
@@ -117,7 +120,10 @@ def _solve(pb, g, L, b, m, mo, rtol, tag):
 
         def setup_saving(problem, grids, u, *a, **k):
             tmp = CHECKPOINT + '.tmp.npz'             # replaced in one step: a kill leaves the last one whole
-            np.savez(tmp, u=u, f0=f0)
+            if CHECKPOINT_F32:
+                np.savez_compressed(tmp, u=u.astype(np.float32), f0=f0)
+            else:
+                np.savez(tmp, u=u, f0=f0)
             os.replace(tmp, CHECKPOINT)
             _log(f'checkpoint written to {CHECKPOINT}')
             return setup(problem, grids, u, *a, **k)
@@ -188,6 +194,9 @@ if __name__ == '__main__':
     if '--progress' in args:
         args.remove('--progress')
         _progress()
+    if '--checkpoint-f32' in args:
+        args.remove('--checkpoint-f32')
+        CHECKPOINT_F32 = True
     for opt in ('--checkpoint', '--resume'):
         if opt in args:
             i = args.index(opt)
