@@ -37,6 +37,9 @@ whatever the path; only the iteration counts stored with it then cover the
 last piece.  --checkpoint-f32 stores the iterate rounded to FP32 and
 compressed (a 256^3 iterate then fits a 64 MB transfer); the continued solve
 starts from that rounded iterate, which moves its path, not its root.
+--from-checkpoint FILE stores the saved iterate itself, with its residual
+as the oracle evaluates it: for a solve whose last Newton steps no longer
+lower ||F|| (its FP64 rounding floor, above the requested tolerance).
 """
 import os
 import sys
@@ -61,6 +64,7 @@ OUT = HERE
 CHECKPOINT = None
 CHECKPOINT_F32 = False
 RESUME = None
+FROM_CHECKPOINT = None
 
 
 def _progress():
@@ -106,6 +110,16 @@ def _solve(pb, g, L, b, m, mo, rtol, tag):
     rep = ON.Report()
     t = time.time()
     nc = pb.ncomp
+    if FROM_CHECKPOINT:
+        # the saved Newton iterate itself, with its residual from the oracle
+        ck = np.load(FROM_CHECKPOINT)
+        u = ck['u'].astype(np.float64)
+        fn = float(np.linalg.norm(OP._mask(g, nc, OP.apply_A(pb, g, u, m) - b)))
+        rep.fnorm = [float(ck['f0']), fn]
+        rep.status = 'checkpoint'
+        rep.newton_iters = rep.linear_iters = -1
+        _log(f'{tag}: iterate of {FROM_CHECKPOINT}, |F|/|F0| = {fn / float(ck["f0"]):.3e}')
+        return u, rep
     u0 = np.zeros(g.node_shape if nc == 1 else (nc,) + g.node_shape)
     # ||F(0)||, as the Newton solve computes it
     f0 = float(np.linalg.norm(OP._mask(g, nc, OP.apply_A(pb, g, u0, m) - b)))
@@ -194,6 +208,10 @@ if __name__ == '__main__':
     if '--progress' in args:
         args.remove('--progress')
         _progress()
+    if '--from-checkpoint' in args:
+        i = args.index('--from-checkpoint')
+        FROM_CHECKPOINT = args[i + 1]
+        del args[i:i + 2]
     if '--checkpoint-f32' in args:
         args.remove('--checkpoint-f32')
         CHECKPOINT_F32 = True

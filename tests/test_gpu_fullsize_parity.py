@@ -17,7 +17,10 @@ Configurations:
   1/2 ||u - u_obs||^2;
 * the p-Laplacian on 256^3 (the benchmark grid), FP32 and FP64 levels;
 * the Neo-Hookean beam 256 x 64 x 64: its first load increment (a tenth of
-  the traction), FP32 levels, to 1e-11.
+  the traction), FP32 levels.  Here the FP64 residual has a rounding floor
+  near 2e-11 ||F_0||: the oracle's last Newton steps no longer lowered it
+  (2.204e-11, then 2.195e-11), so its reference is that iterate, and the GPU
+  solves to 3e-11.
 """
 import os
 
@@ -115,7 +118,7 @@ def test_plap256_solution(prec):
 def test_neohooke_first_increment():
     w = W.WORKLOADS['neohooke-256x64']
     r = _ref('neohooke-256x64')
-    ctx = make_ctx(w, newton_rtol=1e-11)
+    ctx = make_ctx(w, newton_rtol=3e-11)
     t = W.traction(w.get('traction_seed', 2))
     b = api.jfnk_assemble_load(ctx, 1, t)
     b1 = (1.0 / w['load_steps']) * b           # the first increment's load, as the load stepping scales it
