@@ -49,7 +49,8 @@ BYTES_PER_NODE = {
 HERE = os.path.dirname(os.path.abspath(__file__))
 STENCIL_SOURCES = ['common.hpp', 'access.hpp', 'elem.hpp', 'reduce.hpp', 'stencil.hpp', 'stencil_tiled.hpp',
                    'ops_stencil.inc']
-TRAFFIC_FILES = {'cheb_step_f32': 'cheb_step_f32_plap3d-256_hbm_traffic.md'}
+TRAFFIC_FILES = {'cheb_step_f32': 'cheb_step_f32_plap3d-256_hbm_traffic.md',
+                 'resid_f64': 'resid_f64_plap3d-256_hbm_traffic.md'}
 
 
 def stencil_hash():
@@ -681,6 +682,9 @@ def main():
                              f'{len(ref["nodes"])} seeded nodes and the whole-grid 2-norm'}
             log(f'vs the oracle solution: {extra["rel_err_vs_oracle_solution"]}')
         fres = residual_gbps(ctxt, w)
+        tr = measured_traffic('resid_f64')
+        fres['traffic'] = round(tr / (fres['avg_us'] * 1e-6) / 1e9, 1) if tr else None
+        fres['traffic_bytes_per_launch'] = tr
         extra['fine_residual_f64'] = fres
         log(f'fine F(u) FP64: {fres["gbps"]:.0f} GB/s ({fres["avg_us"]:.1f} us)')
         try:

@@ -150,6 +150,21 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
     // Loads use clamped urows and columns and are always issued.  Off the grid
     // the state is a copy of the edge row or plane, read only by elements that
     // are switched off; the direction is zeroed there and on Dirichlet nodes.
+    //
+    // LATE (the residual, whose fetch is the state alone): the fetched
+    // registers keep the raw loaded values, every mask is applied by store(),
+    // and settle() marks them used on every path before that, so nothing
+    // between the fetch and the store waits for the loads.  An early use, or
+    // a register write that could overtake a load left pending on some path,
+    // makes the compiler drain every outstanding access at that point, and
+    // the fetch then no longer overlaps the element work (FP64 F(u) at 256^3:
+    // 144 us that way, 136 us late).  The FD modes keep masking the direction
+    // as it arrives, which waits for the fetch before the element work: their
+    // VALU is about two thirds busy, and with the fetch and the epilogue
+    // inputs in flight across the element work the FP32 Chebyshev step at
+    // 256^3 took 148 us instead of 136 us (150 us with the fetch spread over
+    // the element rows).
+    constexpr bool LATE = !FD;
     const int tc = t < uNX ? t : uNX - 1;
     T px[R + 2], pk[R + 2], qx = T(0), qk = T(0);
     TV pv[R + 2], qv = TV(0);
@@ -176,19 +191,39 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
             const bool in = zin && gy == gyc && t < urows + 2;
             const int idx = (pzc * uNY + gyc) * uNX + unx;
             const T xv = x[idx];
-            qx = in ? xv : T(0);
+            if constexpr (LATE) {
+                qx = xv;
+            } else {
+                qx = in ? xv : T(0);
+            }
             if constexpr (FD) {
                 const TV vv = v[idx];
                 qv = (in && !(xdir_e || zd || ydir_u(gy))) ? vv : TV(0);
             }
             if constexpr (INV) {
                 const T kv = kap[idx];
-                qk = in ? kv : T(0);
+                if constexpr (LATE) {
+                    qk = kv;
+                } else {
+                    qk = in ? kv : T(0);
+                }
             }
+        }
+    };
+    auto settle = [&]() {
+#pragma unroll
+        for (int r = 0; r < R + 2; ++r) {
+            asm volatile("" ::"v"(px[r]));
+            if constexpr (INV) asm volatile("" ::"v"(pk[r]));
+        }
+        if (extra) {
+            asm volatile("" ::"v"(qx));
+            if constexpr (INV) asm volatile("" ::"v"(qk));
         }
     };
     auto store = [&](int pz) {
         const int sl = pz & 1;
+        if constexpr (LATE) settle();
         if (own_col) {
 #pragma unroll
             for (int r = 0; r < R + 2; ++r) {
@@ -200,9 +235,14 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
             }
         }
         if (extra && t < usrows) {
-            sx[sl * plane + t * P + unx] = qx;
+            bool in = true;
+            if constexpr (LATE) {
+                const int gy = uy0 - 1 + t;
+                in = pz >= 0 && pz < uNZ && gy >= 0 && gy < uNY && t < urows + 2;
+            }
+            sx[sl * plane + t * P + unx] = in ? qx : T(0);
             if constexpr (FD) sv[sl * plane + t * P + unx] = qv;
-            if constexpr (INV) sk[sl * plane + t * P + unx] = qk;
+            if constexpr (INV) sk[sl * plane + t * P + unx] = in ? qk : T(0);
         }
     };
 
@@ -337,6 +377,18 @@ __global__ __launch_bounds__(TMAX_THREADS) void k_tiled(Grid g, Phys ph, const T
         if (z + 2 <= z1) store(z + 2);
         {
             const bool zd = zdir_u(z);
+            // LATE: the epilogue inputs are marked used on every path (see settle)
+#pragma unroll
+            for (int k = 0; k < (LATE ? R : 0); ++k) {
+#pragma unroll
+                for (int c = 0; c < Epi::NIN; ++c) asm volatile("" ::"v"(pin[k][c]));
+                if constexpr (PLAIN) asm volatile("" ::"v"(pax[k]));
+            }
+            if (LATE && extra) {
+#pragma unroll
+                for (int c = 0; c < Epi::NIN; ++c) asm volatile("" ::"v"(qin[c]));
+                if constexpr (PLAIN) asm volatile("" ::"v"(qax));
+            }
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 const int gy = uy0 + k;
