@@ -15,11 +15,11 @@ Configurations:
 * the inverse-coefficient problem on 128^3: u(m), u(m_obs), the adjoint state
   lam of J(u)^T lam = u - u_obs and the gradient -(dF/dm)^T lam of
   1/2 ||u - u_obs||^2;
-* the p-Laplacian on 256^3 (the benchmark grid), FP32 and FP64 levels.  The
-  oracle's reference is the Newton iterate at ||F|| = 3.15e-12 ||F_0||: its
-  next Newton step was asked for a linear reduction of 3e-12, at the limit of
-  the FD Jacobian action, and had not ended after 35 V-cycles (26 minutes on
-  one core).  The GPU solves to 1e-11 (it stops near 4e-12).
+* the p-Laplacian on 256^3 (the benchmark grid), FP32 and FP64 levels.  Here
+  the FP64 residual has a rounding floor near 3.1e-12 ||F_0||: the oracle's
+  tenth Newton step (23 V-cycles) moved u by 7e-16 relative and left ||F||
+  at 3.147e-12 (from 3.153e-12), so its reference is the iterate after nine
+  steps, and the GPU solves to 1e-11 (it stops near 4e-12).
 * the Neo-Hookean beam 256 x 64 x 64: its first load increment (a tenth of
   the traction), FP32 levels.  Here the FP64 residual has a rounding floor
   near 2e-11 ||F_0||: the oracle's last Newton steps no longer lowered it
