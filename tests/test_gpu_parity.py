@@ -25,7 +25,7 @@ from oracle import derivatives as OD
 from oracle import mg as OM
 from oracle import problems as OP
 from oracle import transfer as OT
-from paper_2103_13890_amd import api
+from paper_2103_13890_amd import _lib, api
 from paper_2103_13890_amd import workloads as W
 
 KINDS = ['bratu2d', 'bratu3d', 'plap', 'plap_gauss', 'minsurf', 'invcoef', 'neohooke']
@@ -343,6 +343,23 @@ def test_gaussian_load():
     c, wd, a = W.gaussian_params(1, 16, 3)
     b = api.jfnk_assemble_load(ctx, 0, W.gaussian_param_array(c, wd, a))
     ref = OP.load_from_function(oracle_grid(w), OP.gaussian_source(c, wd, a))
+    assert rel(to_np(b), ref) < 1e-13
+
+
+def test_load_parameters_beyond_grid_refused():
+    # 16 sources x 5 parameters = 80 doubles against a 3^3-node grid: the
+    # parameters are staged in a node-sized device buffer, so the call is
+    # refused before any copy or launch
+    w = W.scaled('plap3d-128', (2, 2, 2), nlevels=1)
+    ctx = make_ctx(w)
+    c, wd, a = W.gaussian_params(1, 16, 3)
+    with pytest.raises(api.JfnkError) as err:
+        api.jfnk_assemble_load(ctx, 0, W.gaussian_param_array(c, wd, a))
+    assert err.value.status == _lib.E_INVAL
+    # one source (5 doubles) fits and matches the oracle
+    c1, wd1, a1 = c[:1], wd[:1], a[:1]
+    b = api.jfnk_assemble_load(ctx, 0, W.gaussian_param_array(c1, wd1, a1))
+    ref = OP.load_from_function(oracle_grid(w), OP.gaussian_source(c1, wd1, a1))
     assert rel(to_np(b), ref) < 1e-13
 
 
